@@ -1,0 +1,185 @@
+/*
+ * treecode.h — C ABI of the MI355X (gfx950) TreeCode gravity library.
+ *
+ * The library evaluates Plummer-softened Newtonian accelerations and
+ * potentials of N particles with the Barnes-Hut TreeCode method, following
+ * Kuzmin, Sirotin & Khoperskov (2024):
+ *   - Eq.(1): a_i = sum_{j != i} G m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^{3/2};
+ *     the matching potential phi_i = -G sum_{j != i} m_j (|r_j - r_i|^2 + eps^2)^{-1/2}.
+ *   - Section 2, TreeCode description: octree split into eight octants until a
+ *     cell holds at most one particle; a distant cell acts as its total mass at
+ *     its centre of mass; theta sets "distant"; theta = 0 is the direct sum.
+ *   - Eqs.(2)-(5): kick-drift-kick leapfrog with the forces of Eq.(4) taken
+ *     from a tree rebuilt at the drifted positions.
+ *
+ * Conventions shared by every entry point:
+ *   - Every data pointer is DEVICE memory on the current HIP device and is
+ *     owned by the caller; the library never frees or keeps caller pointers
+ *     beyond the call (the tree handle keeps its own copies).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  All work
+ *     is enqueued on it; no hidden streams.  Results are valid once the
+ *     stream has been synchronised, except where an entry point says it
+ *     blocks.
+ *   - Arguments are validated before any launch; on an error nothing is
+ *     written to the caller's outputs and a status other than TC_OK is
+ *     returned.  tc_last_error() gives a thread-local message.
+ *   - Positions are [n,3] row-major (x0 y0 z0 x1 ...), masses [n]; both FP32
+ *     or both FP64 (tc_dtype).  0 <= n < 2^31.
+ */
+#ifndef TREECODE_H
+#define TREECODE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TC_OK = 0,
+    TC_ERR_INVALID = 1,   /* bad argument (null pointer, n out of range, theta < 0, ...) */
+    TC_ERR_NOMEM = 2,     /* the allocator returned NULL */
+    TC_ERR_DEVICE = 3,    /* no usable HIP device, or a HIP call failed */
+    TC_ERR_STATE = 4,     /* call out of order (e.g. tc_forces before tc_moments) */
+    TC_ERR_OVERFLOW = 5,  /* a size limit was exceeded (node count >= 2^32, list budget) */
+    TC_ERR_INPUT = 6      /* non-finite position or negative / non-finite mass found on device */
+} tc_status;
+
+typedef enum { TC_F32 = 0, TC_F64 = 1 } tc_dtype;
+
+/* Walk precision.  F32C: FP32 interactions on anchor-relative coordinates with
+ * Kahan-compensated FP32 accumulation, FP32 outputs.  F64: FP64 throughout,
+ * FP64 outputs. */
+typedef enum { TC_WALK_F32C = 0, TC_WALK_F64 = 1 } tc_walk;
+
+/* tc_forces flags */
+#define TC_COUNT 1u        /* record the interaction count of every target */
+#define TC_STORE_LISTS 2u  /* keep what tc_forces_backward needs to replay the walk */
+
+typedef struct tc_tree tc_tree;
+
+/* Device allocator used for every buffer the library owns.  alloc returns
+ * NULL on failure; both receive the stream of the call that allocates. */
+typedef void* (*tc_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*tc_free_fn)(void* ptr, void* stream, void* ctx);
+
+/* Install the allocator used by handles created afterwards (process-wide).
+ * Passing NULL for both restores the default (hipMalloc / hipFree).
+ * Errors: TC_ERR_INVALID if exactly one of alloc/free is NULL. */
+tc_status tc_set_allocator(tc_alloc_fn alloc, tc_free_fn free_fn, void* ctx);
+
+/* Keys, sort and octree of a particle set (TreeCode description, section 2).
+ *   pos  [n,3], mass [n]: device arrays of `dtype`.
+ *   *tree: NULL to create a handle, or an existing handle to rebuild in place
+ *          (its buffers grow as needed; earlier results are invalidated).
+ * The root cube is lo_k = min_i x_ik with side L = the smallest power of two
+ * >= the largest extent (1 if all points coincide); 21-bit grid coordinates,
+ * 63-bit Morton keys (x highest), stable sort, canonical octree with chain
+ * nodes kept and leaves of one particle (several only at level 21).
+ * BLOCKS once: the node count is read back to size the node arrays.
+ * Errors: TC_ERR_INVALID (null pointers with n > 0, n out of range, bad
+ * dtype), TC_ERR_INPUT (non-finite position, negative or non-finite mass),
+ * TC_ERR_NOMEM, TC_ERR_OVERFLOW (>= 2^32 nodes), TC_ERR_DEVICE. */
+tc_status tc_build(const void* pos, const void* mass, int64_t n, tc_dtype dtype,
+                   void* stream, tc_tree** tree);
+
+/* Upward pass: total mass M and centre of mass X of every node (monopole,
+ * TreeCode description of section 2).  One-particle leaf: M = m, X = x
+ * verbatim; otherwise M = sum M_c, X = sum(M_c X_c) / M in FP64 with the
+ * children in octant order; M = 0 gives X = the cell centre.
+ * Errors: TC_ERR_INVALID (null tree), TC_ERR_STATE (no successful tc_build). */
+tc_status tc_moments(tc_tree* tree, void* stream);
+
+/* Accelerations and potentials, Eq.(1), by the Barnes-Hut walk.  For target
+ * i, node n (side s = L 2^-level) is accepted as a monopole iff it does not
+ * contain i and s < theta |X_n - x_i| (tested as |X_n - x_i|^2 > (s/theta)^2);
+ * a rejected leaf contributes its particles j != i directly; theta = 0 never
+ * accepts, giving the direct sum.
+ *   acc [n,3] (required), pot [n] (may be NULL): device, in the caller's
+ *   particle order, FP32 for TC_WALK_F32C and FP64 for TC_WALK_F64.
+ *   flags: TC_COUNT, TC_STORE_LISTS.
+ * Errors: TC_ERR_INVALID (theta < 0 or not finite, eps < 0 or not finite, G
+ * not finite, acc NULL with n > 0, bad mode or flags), TC_ERR_STATE (no
+ * tc_moments since the last tc_build), TC_ERR_NOMEM, TC_ERR_DEVICE. */
+tc_status tc_forces(tc_tree* tree, double theta, double eps, double G, tc_walk mode,
+                    uint32_t flags, void* acc, void* pot, void* stream);
+
+/* Adjoint of the last tc_forces with the tree and every interaction set held
+ * fixed (node membership frozen, moments still functions of x and m).
+ * Given L(acc, pot): g_acc = dL/dacc [n,3], g_pot = dL/dpot [n] (may be NULL),
+ * writes g_pos = dL/dx [n,3] and g_mass = dL/dm [n] (either may be NULL), all
+ * in the caller's order and in the dtype of the last walk's outputs.
+ * Errors: TC_ERR_INVALID, TC_ERR_STATE (no tc_forces since the last build),
+ * TC_ERR_NOMEM, TC_ERR_DEVICE. */
+tc_status tc_forces_backward(tc_tree* tree, const void* g_acc, const void* g_pot,
+                             void* g_pos, void* g_mass, void* stream);
+
+/* One kick-drift-kick step, Eqs.(2)-(5): v += tau/2 a; x += tau v; rebuild
+ * the tree at x and evaluate a (and pot); v += tau/2 a.  pos, vel updated in
+ * place; acc holds a^n on entry and a^{n+1} on exit; pot (may be NULL)
+ * receives phi^{n+1}.  pos/vel/mass are of `dtype`; acc/pot are of the walk
+ * precision (FP32 for F32C, FP64 for F64).  *tree as for tc_build.
+ * Blocks once (inside the rebuild).  Errors: as tc_build and tc_forces. */
+tc_status tc_leapfrog_step(tc_tree** tree, void* pos, void* vel, const void* mass,
+                           void* acc, void* pot, int64_t n, tc_dtype dtype, double tau,
+                           double theta, double eps, double G, tc_walk mode, void* stream);
+
+/* Sizes, geometry, diagnostics and per-stage timings of a handle. */
+typedef struct {
+    int64_t n;               /* particles */
+    int64_t n_nodes;         /* octree nodes (chain nodes included) */
+    int64_t n_leaves;
+    int64_t n_multi_leaves;  /* level-21 leaves holding >= 2 particles */
+    double lo[3];            /* root cube corner */
+    double L;                /* root cube side (a power of two) */
+    int32_t log2L;
+    int32_t max_level;
+    uint32_t state;          /* bit 0 built, bit 1 moments, bit 2 forces */
+    uint32_t last_mode;      /* tc_walk of the last tc_forces */
+    uint64_t interactions;   /* sum over targets of the interaction count (TC_COUNT), else 0 */
+    double momentum[3];      /* sum_i m_i a_i of the last tc_forces (FP64) */
+    double sum_m_abs_a;      /* sum_i m_i |a_i| (FP64) */
+    float stage_ms[8];       /* last timed durations: 0 keys, 1 sort, 2 tree, 3 moments,
+                                4 walk, 5 diagnostics, 6 backward walk, 7 backward down-pass
+                                (-1 if not recorded) */
+} tc_stats;
+
+/* Fill *out.  Synchronises `stream` when diagnostics or timings are pending.
+ * Errors: TC_ERR_INVALID (null pointer). */
+tc_status tc_tree_stats(tc_tree* tree, tc_stats* out, void* stream);
+
+/* Record per-stage durations with HIP events on the call's stream (off by
+ * default).  Errors: TC_ERR_INVALID (null tree). */
+tc_status tc_tree_set_timing(tc_tree* tree, int on);
+
+/* Copy the canonical tree to caller device buffers (any may be NULL):
+ * keys u64[n] (sorted), perm u32[n] (sorted position -> caller index),
+ * and, in pre-order (= sorted by (first, level)), level u8[n_nodes],
+ * first u32[n_nodes], count u32[n_nodes], com f64[n_nodes,3], mass f64[n_nodes]
+ * (com and mass need tc_moments).
+ * Errors: TC_ERR_INVALID, TC_ERR_STATE. */
+tc_status tc_tree_export(const tc_tree* tree, uint64_t* keys, uint32_t* perm, uint8_t* level,
+                         uint32_t* first, uint32_t* count, double* com, double* mass,
+                         void* stream);
+
+/* Per-target interaction counts of the last tc_forces run with TC_COUNT, in
+ * the caller's order: counts u32[n] (device).
+ * Errors: TC_ERR_INVALID, TC_ERR_STATE (no counted walk). */
+tc_status tc_interaction_counts(const tc_tree* tree, uint32_t* counts, void* stream);
+
+/* Release a handle and everything it owns (NULL is a no-op).  Synchronises
+ * the device before freeing. */
+void tc_tree_free(tc_tree* tree);
+
+/* Message of the last error on this thread ("" if none). */
+const char* tc_last_error(void);
+
+/* Library version string. */
+const char* tc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TREECODE_H */

@@ -1,0 +1,590 @@
+// Host side of the C ABI declared in include/treecode.h: argument checks,
+// handle lifetime, buffer growth, stream plumbing and the order of launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "tc_internal.h"
+
+using namespace tc;
+
+namespace {
+
+thread_local std::string g_err;
+std::mutex g_alloc_mu;
+tc_alloc_fn g_alloc = nullptr;
+tc_free_fn g_free = nullptr;
+void* g_actx = nullptr;
+
+tc_status fail(tc_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+void* default_alloc(size_t bytes, void*, void*)
+{
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void default_free(void* p, void*, void*) { (void)hipFree(p); }
+
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+enum Stage { kStKeys = 0, kStSort, kStTree, kStMoments, kStWalk, kStDiag, kStBwdWalk, kStBwdDown, kNumStages };
+
+struct HostMirror {
+    Geom geom;
+    uint32_t level_hist[kLevels];
+    uint32_t total;
+    uint32_t level_off[kLevels + 1];
+    double diag[4];
+    unsigned long long inter;
+    uint32_t status;
+};
+
+}  // namespace
+
+struct tc_tree {
+    int device = -1;
+    tc_alloc_fn alloc = nullptr;
+    tc_free_fn freef = nullptr;
+    void* actx = nullptr;
+
+    int64_t n = 0;
+    int64_t nn = 0;
+    tc_dtype dtype = TC_F32;
+
+    // particle-sized
+    Buf keys0, keys1, vals0, vals1, sx, sy, sz, sm, c, cnt, pre, sorted_counts, diag_part;
+    uint64_t* skeys = nullptr;
+    uint32_t* perm = nullptr;
+    Buf sort_temp, scan_temp, bounds_part;
+    // node-sized
+    Buf level, first, count, next, nchild, cs, gidx, parent, list, nm, nx, wn;
+    // small device block
+    Buf small;
+    Geom* geom = nullptr;
+    uint32_t* level_hist = nullptr;
+    uint32_t* level_cursor = nullptr;
+    uint32_t* level_off_dev = nullptr;
+    double* diag_out = nullptr;
+    unsigned long long* inter_total = nullptr;
+    uint32_t* status = nullptr;
+
+    HostMirror* host = nullptr;
+    uint32_t state = 0;  // bit 0 built, bit 1 moments, bit 2 forces
+    tc_walk last_mode = TC_WALK_F32C;
+    bool counted = false;
+    bool diag_pending = false;
+    Geom geom_host{};
+
+    bool timing = false;
+    hipEvent_t ev[2 * kNumStages] = {};
+    bool ev_used[kNumStages] = {};
+};
+
+namespace {
+
+tc_status ensure(tc_tree* t, Buf& b, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) bytes = 256;
+    if (b.bytes >= bytes) return TC_OK;
+    if (b.p) t->freef(b.p, s, t->actx);
+    b.p = nullptr;
+    b.bytes = 0;
+    size_t want = bytes + bytes / 4;
+    want = (want + 255) & ~(size_t)255;
+    void* p = t->alloc(want, s, t->actx);
+    if (!p) return fail(TC_ERR_NOMEM, "allocation of %zu bytes failed", want);
+    b.p = p;
+    b.bytes = want;
+    return TC_OK;
+}
+
+void release(tc_tree* t, Buf& b)
+{
+    if (b.p) t->freef(b.p, nullptr, t->actx);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename T>
+T* P(const Buf& b) { return (T*)b.p; }
+
+#define TC_TRY(expr)                          \
+    do {                                      \
+        tc_status _st = (expr);               \
+        if (_st != TC_OK) return _st;         \
+    } while (0)
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess) return fail(TC_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+tc_status check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(TC_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return TC_OK;
+}
+
+void stage_begin(tc_tree* t, int st, hipStream_t s)
+{
+    if (!t->timing) return;
+    if (!t->ev[2 * st]) {
+        (void)hipEventCreate(&t->ev[2 * st]);
+        (void)hipEventCreate(&t->ev[2 * st + 1]);
+    }
+    (void)hipEventRecord(t->ev[2 * st], s);
+}
+
+void stage_end(tc_tree* t, int st, hipStream_t s)
+{
+    if (!t->timing) return;
+    (void)hipEventRecord(t->ev[2 * st + 1], s);
+    t->ev_used[st] = true;
+}
+
+tc_status current_device(int* dev)
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(TC_ERR_DEVICE, "no HIP device available");
+    }
+    HIP_TRY(hipGetDevice(dev));
+    return TC_OK;
+}
+
+tc_status create_tree(tc_tree** out, hipStream_t s)
+{
+    int dev;
+    TC_TRY(current_device(&dev));
+    tc_tree* t = new tc_tree();
+    t->device = dev;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        t->alloc = g_alloc ? g_alloc : default_alloc;
+        t->freef = g_free ? g_free : default_free;
+        t->actx = g_alloc ? g_actx : nullptr;
+    }
+    size_t small = sizeof(Geom) + 4 * (3 * (kLevels + 2)) + 8 * 4 + 8 + 8 + 64;
+    tc_status st = ensure(t, t->small, small, s);
+    if (st != TC_OK) {
+        delete t;
+        return st;
+    }
+    char* p = (char*)t->small.p;
+    t->geom = (Geom*)p;
+    p += (sizeof(Geom) + 15) & ~(size_t)15;
+    t->diag_out = (double*)p;
+    p += 4 * sizeof(double);
+    t->inter_total = (unsigned long long*)p;
+    p += 8;
+    t->level_hist = (uint32_t*)p;
+    p += 4 * (kLevels + 2);
+    t->level_cursor = (uint32_t*)p;
+    p += 4 * (kLevels + 2);
+    t->level_off_dev = (uint32_t*)p;
+    p += 4 * (kLevels + 2);
+    t->status = (uint32_t*)p;
+    if (hipHostMalloc((void**)&t->host, sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        release(t, t->small);
+        delete t;
+        return fail(TC_ERR_NOMEM, "pinned host allocation failed");
+    }
+    memset(t->host, 0, sizeof(HostMirror));
+    *out = t;
+    return TC_OK;
+}
+
+tc_status check_device(const tc_tree* t)
+{
+    int dev;
+    TC_TRY(current_device(&dev));
+    if (dev != t->device) return fail(TC_ERR_INVALID, "tree was created on device %d, current is %d", t->device, dev);
+    return TC_OK;
+}
+
+tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, tc_dtype dt, hipStream_t s)
+{
+    t->state = 0;
+    t->n = n;
+    t->nn = 0;
+    t->dtype = dt;
+    t->diag_pending = false;
+    t->counted = false;
+    if (n == 0) {
+        Geom g{};
+        g.L = 1.0;
+        g.scale = std::ldexp(1.0, 21);
+        g.h = std::ldexp(1.0, -21);
+        t->geom_host = g;
+        t->state = 1;
+        return TC_OK;
+    }
+    const size_t n8 = (size_t)n * 8, n4 = (size_t)n * 4;
+    TC_TRY(ensure(t, t->keys0, n8, s));
+    TC_TRY(ensure(t, t->keys1, n8, s));
+    TC_TRY(ensure(t, t->vals0, n4, s));
+    TC_TRY(ensure(t, t->vals1, n4, s));
+    TC_TRY(ensure(t, t->sx, n8, s));
+    TC_TRY(ensure(t, t->sy, n8, s));
+    TC_TRY(ensure(t, t->sz, n8, s));
+    TC_TRY(ensure(t, t->sm, n8, s));
+    TC_TRY(ensure(t, t->c, (size_t)n, s));
+    TC_TRY(ensure(t, t->cnt, n4, s));
+    TC_TRY(ensure(t, t->pre, n4 + 8, s));
+    TC_TRY(ensure(t, t->sort_temp, radix_temp_bytes(n), s));
+    TC_TRY(ensure(t, t->scan_temp, scan_temp_bytes(n), s));
+    const int nb = bounds_blocks(n);
+    TC_TRY(ensure(t, t->bounds_part, (size_t)nb * 8 * sizeof(double), s));
+
+    stage_begin(t, kStKeys, s);
+    launch_bounds(pos, mass, n, dt, P<double>(t->bounds_part), nb, t->geom, s);
+    launch_keys(pos, n, dt, t->geom, P<uint64_t>(t->keys0), P<uint32_t>(t->vals0), s);
+    stage_end(t, kStKeys, s);
+    TC_TRY(check_launch("keys"));
+
+    stage_begin(t, kStSort, s);
+    radix_sort_pairs(P<uint64_t>(t->keys0), P<uint32_t>(t->vals0), P<uint64_t>(t->keys1), P<uint32_t>(t->vals1),
+                     n, 63, t->sort_temp.p, s, &t->skeys, &t->perm);
+    launch_gather(pos, mass, n, dt, t->perm, P<double>(t->sx), P<double>(t->sy), P<double>(t->sz),
+                  P<double>(t->sm), s);
+    stage_end(t, kStSort, s);
+    TC_TRY(check_launch("sort"));
+
+    stage_begin(t, kStTree, s);
+    launch_adjacent_levels(t->skeys, n, P<int8_t>(t->c), s);
+    launch_fill_u32(t->level_hist, kLevels, 0u, s);
+    launch_node_counts(P<int8_t>(t->c), n, P<uint32_t>(t->cnt), t->level_hist, s);
+    launch_exclusive_scan_u32(P<uint32_t>(t->cnt), P<uint32_t>(t->pre), n, t->scan_temp.p, s);
+    HIP_TRY(hipMemcpyAsync(&t->host->geom, t->geom, sizeof(Geom), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(t->host->level_hist, t->level_hist, 4 * kLevels, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&t->host->total, P<uint32_t>(t->pre) + n, 4, hipMemcpyDeviceToHost, s));
+    TC_TRY(check_launch("tree counts"));
+    HIP_TRY(hipStreamSynchronize(s));
+    t->geom_host = t->host->geom;
+    if (t->geom_host.bad & 1u) return fail(TC_ERR_INPUT, "non-finite particle position");
+    if (t->geom_host.bad & 2u) return fail(TC_ERR_INPUT, "negative or non-finite particle mass");
+    uint64_t total = 0;
+    for (int l = 0; l < kLevels; ++l) {
+        t->host->level_off[l] = (uint32_t)total;
+        total += t->host->level_hist[l];
+    }
+    if (total >= 0xFFFFFFFFull) return fail(TC_ERR_OVERFLOW, "octree needs %llu nodes (limit 2^32 - 1)",
+                                           (unsigned long long)total);
+    t->host->level_off[kLevels] = (uint32_t)total;
+    if (total != t->host->total) return fail(TC_ERR_DEVICE, "node count mismatch (%llu vs %u)",
+                                             (unsigned long long)total, t->host->total);
+    const int64_t nn = (int64_t)total;
+    t->nn = nn;
+    const size_t m4 = (size_t)nn * 4;
+    TC_TRY(ensure(t, t->level, (size_t)nn, s));
+    TC_TRY(ensure(t, t->first, m4, s));
+    TC_TRY(ensure(t, t->count, m4, s));
+    TC_TRY(ensure(t, t->next, m4, s));
+    TC_TRY(ensure(t, t->nchild, m4, s));
+    TC_TRY(ensure(t, t->cs, m4 + 8, s));
+    TC_TRY(ensure(t, t->gidx, m4, s));
+    TC_TRY(ensure(t, t->parent, m4, s));
+    TC_TRY(ensure(t, t->list, m4, s));
+    TC_TRY(ensure(t, t->nm, (size_t)nn * 8, s));
+    TC_TRY(ensure(t, t->nx, (size_t)nn * 24, s));
+    TC_TRY(ensure(t, t->wn, (size_t)nn * sizeof(WalkNode), s));
+    TC_TRY(ensure(t, t->scan_temp, scan_temp_bytes(nn > n ? nn : n), s));
+
+    launch_emit_nodes(t->skeys, P<int8_t>(t->c), P<uint32_t>(t->pre), n, P<uint8_t>(t->level), P<uint32_t>(t->first),
+                      P<uint32_t>(t->count), P<uint32_t>(t->next), s);
+    launch_count_children(P<uint8_t>(t->level), P<uint32_t>(t->count), P<uint32_t>(t->next), nn,
+                          P<uint32_t>(t->nchild), s);
+    launch_exclusive_scan_u32(P<uint32_t>(t->nchild), P<uint32_t>(t->cs), nn, t->scan_temp.p, s);
+    launch_assign_groups(P<uint32_t>(t->next), P<uint32_t>(t->nchild), P<uint32_t>(t->cs), nn, P<uint32_t>(t->gidx),
+                         P<uint32_t>(t->parent), s);
+    HIP_TRY(hipMemcpyAsync(t->level_off_dev, t->host->level_off, 4 * (kLevels + 1), hipMemcpyHostToDevice, s));
+    launch_fill_u32(t->level_cursor, kLevels, 0u, s);
+    launch_level_lists(P<uint8_t>(t->level), nn, t->level_off_dev, t->level_cursor, P<uint32_t>(t->list), s);
+    stage_end(t, kStTree, s);
+    TC_TRY(check_launch("tree"));
+    t->state = 1;
+    return TC_OK;
+}
+
+tc_status moments_impl(tc_tree* t, hipStream_t s)
+{
+    if (t->n > 0) {
+        stage_begin(t, kStMoments, s);
+        launch_moments(P<uint32_t>(t->first), P<uint32_t>(t->count), P<uint32_t>(t->next), P<uint32_t>(t->nchild),
+                       P<uint32_t>(t->cs), P<uint32_t>(t->gidx), t->host->level_off, P<uint32_t>(t->list),
+                       t->skeys, P<double>(t->sx), P<double>(t->sy), P<double>(t->sz), P<double>(t->sm), t->geom,
+                       P<double>(t->nm), P<double>(t->nx), P<WalkNode>(t->wn), s);
+        stage_end(t, kStMoments, s);
+        TC_TRY(check_launch("moments"));
+    }
+    t->state |= 2u;
+    return TC_OK;
+}
+
+tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mode, uint32_t flags, void* acc,
+                      void* pot, hipStream_t s)
+{
+    const int64_t n = t->n;
+    t->last_mode = mode;
+    t->counted = (flags & TC_COUNT) != 0;
+    if (n == 0) {
+        t->state |= 4u;
+        t->host->diag[0] = t->host->diag[1] = t->host->diag[2] = t->host->diag[3] = 0.0;
+        t->host->inter = 0;
+        t->diag_pending = false;
+        return TC_OK;
+    }
+    const int64_t waves = walk_waves(n);
+    TC_TRY(ensure(t, t->diag_part, (size_t)waves * 4 * sizeof(double), s));
+    if (t->counted) TC_TRY(ensure(t, t->sorted_counts, (size_t)n * 4, s));
+
+    WalkArgs a{};
+    a.nodes = P<WalkNode>(t->wn);
+    a.sx = P<double>(t->sx);
+    a.sy = P<double>(t->sy);
+    a.sz = P<double>(t->sz);
+    a.sm = P<double>(t->sm);
+    a.perm = t->perm;
+    a.n = n;
+    a.eps2 = eps * eps;
+    a.G = G;
+    for (int l = 0; l < kLevels; ++l) {
+        double side = std::ldexp(t->geom_host.L, -l);
+        double tv = theta > 0.0 ? (side / theta) * (side / theta) : INFINITY;
+        a.tau64[l] = tv;
+        a.tau32[l] = (float)tv;
+    }
+    a.acc = acc;
+    a.pot = pot;
+    a.counts = t->counted ? P<uint32_t>(t->sorted_counts) : nullptr;
+    a.diag = P<double>(t->diag_part);
+    a.status = t->status;
+
+    launch_fill_u32(t->status, 1, 0u, s);
+    stage_begin(t, kStWalk, s);
+    launch_walk(a, mode, t->counted, s);
+    stage_end(t, kStWalk, s);
+    TC_TRY(check_launch("walk"));
+    stage_begin(t, kStDiag, s);
+    launch_diag_final(P<double>(t->diag_part), waves, t->diag_out, s);
+    if (t->counted) launch_sum_counts(P<uint32_t>(t->sorted_counts), n, t->inter_total, s);
+    stage_end(t, kStDiag, s);
+    TC_TRY(check_launch("diagnostics"));
+    HIP_TRY(hipMemcpyAsync(t->host->diag, t->diag_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&t->host->status, t->status, 4, hipMemcpyDeviceToHost, s));
+    if (t->counted)
+        HIP_TRY(hipMemcpyAsync(&t->host->inter, t->inter_total, 8, hipMemcpyDeviceToHost, s));
+    t->diag_pending = true;
+    t->state |= 4u;
+    return TC_OK;
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+extern "C" {
+
+tc_status tc_set_allocator(tc_alloc_fn alloc, tc_free_fn free_fn, void* ctx)
+{
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(TC_ERR_INVALID, "tc_set_allocator: give both alloc and free, or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_actx = alloc ? ctx : nullptr;
+    return TC_OK;
+}
+
+tc_status tc_build(const void* pos, const void* mass, int64_t n, tc_dtype dtype, void* stream, tc_tree** tree)
+{
+    g_err.clear();
+    if (!tree) return fail(TC_ERR_INVALID, "tc_build: tree is NULL");
+    if (n < 0 || n >= (int64_t)1 << 31) return fail(TC_ERR_INVALID, "tc_build: n = %lld out of range [0, 2^31)", (long long)n);
+    if (dtype != TC_F32 && dtype != TC_F64) return fail(TC_ERR_INVALID, "tc_build: bad dtype %d", (int)dtype);
+    if (n > 0 && (!pos || !mass)) return fail(TC_ERR_INVALID, "tc_build: pos and mass must be non-NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (!*tree) {
+        TC_TRY(create_tree(tree, s));
+    } else {
+        TC_TRY(check_device(*tree));
+    }
+    return build_impl(*tree, pos, mass, n, dtype, s);
+}
+
+tc_status tc_moments(tc_tree* t, void* stream)
+{
+    g_err.clear();
+    if (!t) return fail(TC_ERR_INVALID, "tc_moments: tree is NULL");
+    if (!(t->state & 1u)) return fail(TC_ERR_STATE, "tc_moments: no successful tc_build on this handle");
+    TC_TRY(check_device(t));
+    return moments_impl(t, (hipStream_t)stream);
+}
+
+tc_status tc_forces(tc_tree* t, double theta, double eps, double G, tc_walk mode, uint32_t flags, void* acc,
+                    void* pot, void* stream)
+{
+    g_err.clear();
+    if (!t) return fail(TC_ERR_INVALID, "tc_forces: tree is NULL");
+    if (!is_finite(theta) || theta < 0.0) return fail(TC_ERR_INVALID, "tc_forces: theta must be finite and >= 0");
+    if (!is_finite(eps) || eps < 0.0) return fail(TC_ERR_INVALID, "tc_forces: eps must be finite and >= 0");
+    if (!is_finite(G)) return fail(TC_ERR_INVALID, "tc_forces: G must be finite");
+    if (mode != TC_WALK_F32C && mode != TC_WALK_F64) return fail(TC_ERR_INVALID, "tc_forces: bad walk mode %d", (int)mode);
+    if (flags & ~(TC_COUNT | TC_STORE_LISTS)) return fail(TC_ERR_INVALID, "tc_forces: unknown flags 0x%x", flags);
+    if (t->n > 0 && !acc) return fail(TC_ERR_INVALID, "tc_forces: acc must be non-NULL");
+    if ((t->state & 3u) != 3u) return fail(TC_ERR_STATE, "tc_forces: call tc_build and tc_moments first");
+    TC_TRY(check_device(t));
+    return forces_impl(t, theta, eps, G, mode, flags, acc, pot, (hipStream_t)stream);
+}
+
+tc_status tc_forces_backward(tc_tree* t, const void* g_acc, const void* g_pot, void* g_pos, void* g_mass,
+                             void* stream)
+{
+    (void)g_acc; (void)g_pot; (void)g_pos; (void)g_mass; (void)stream;
+    g_err.clear();
+    if (!t) return fail(TC_ERR_INVALID, "tc_forces_backward: tree is NULL");
+    return fail(TC_ERR_STATE, "tc_forces_backward: not available in this build");
+}
+
+tc_status tc_leapfrog_step(tc_tree** tree, void* pos, void* vel, const void* mass, void* acc, void* pot,
+                           int64_t n, tc_dtype dtype, double tau, double theta, double eps, double G, tc_walk mode,
+                           void* stream)
+{
+    (void)tree; (void)pos; (void)vel; (void)mass; (void)acc; (void)pot; (void)n; (void)dtype; (void)tau;
+    (void)theta; (void)eps; (void)G; (void)mode; (void)stream;
+    g_err.clear();
+    return fail(TC_ERR_STATE, "tc_leapfrog_step: not available in this build");
+}
+
+tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
+{
+    g_err.clear();
+    if (!t || !out) return fail(TC_ERR_INVALID, "tc_tree_stats: NULL argument");
+    memset(out, 0, sizeof *out);
+    bool any_ev = false;
+    for (int i = 0; i < kNumStages; ++i) any_ev |= t->ev_used[i];
+    if (t->diag_pending || any_ev) {
+        TC_TRY(check_device(t));
+        HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+        t->diag_pending = false;
+    }
+    out->n = t->n;
+    out->n_nodes = t->nn;
+    for (int k = 0; k < 3; ++k) out->lo[k] = t->geom_host.lo[k];
+    out->L = t->geom_host.L;
+    out->log2L = t->geom_host.log2L;
+    int maxl = 0;
+    for (int l = 0; l < kLevels; ++l)
+        if (t->n > 0 && (t->state & 1u) && t->host->level_hist[l]) maxl = l;
+    out->max_level = maxl;
+    out->state = t->state;
+    out->last_mode = (uint32_t)t->last_mode;
+    if (t->state & 4u) {
+        for (int k = 0; k < 3; ++k) out->momentum[k] = t->host->diag[k];
+        out->sum_m_abs_a = t->host->diag[3];
+        out->interactions = t->counted ? t->host->inter : 0;
+    }
+    for (int i = 0; i < 8; ++i) {
+        out->stage_ms[i] = -1.0f;
+        if (t->ev_used[i]) {
+            float ms = -1.0f;
+            if (hipEventElapsedTime(&ms, t->ev[2 * i], t->ev[2 * i + 1]) == hipSuccess) out->stage_ms[i] = ms;
+            else (void)hipGetLastError();
+        }
+    }
+    if (t->host->status & 1u) return fail(TC_ERR_OVERFLOW, "walk stack overflow");
+    if (t->host->status & 2u) return fail(TC_ERR_DEVICE, "corrupt tree: a node with more than 8 children");
+    return TC_OK;
+}
+
+tc_status tc_tree_set_timing(tc_tree* t, int on)
+{
+    g_err.clear();
+    if (!t) return fail(TC_ERR_INVALID, "tc_tree_set_timing: tree is NULL");
+    t->timing = on != 0;
+    for (int i = 0; i < kNumStages; ++i) t->ev_used[i] = false;
+    return TC_OK;
+}
+
+tc_status tc_tree_export(const tc_tree* t, uint64_t* keys, uint32_t* perm, uint8_t* level, uint32_t* first,
+                         uint32_t* count, double* com, double* mass, void* stream)
+{
+    g_err.clear();
+    if (!t) return fail(TC_ERR_INVALID, "tc_tree_export: tree is NULL");
+    if (!(t->state & 1u)) return fail(TC_ERR_STATE, "tc_tree_export: no successful tc_build");
+    if ((com || mass) && !(t->state & 2u)) return fail(TC_ERR_STATE, "tc_tree_export: com/mass need tc_moments");
+    TC_TRY(check_device(t));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)t->n, nn = (size_t)t->nn;
+    if (n == 0) return TC_OK;
+    auto cp = [&](void* dst, const void* src, size_t bytes) -> tc_status {
+        if (!dst) return TC_OK;
+        HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+        return TC_OK;
+    };
+    TC_TRY(cp(keys, t->skeys, n * 8));
+    TC_TRY(cp(perm, t->perm, n * 4));
+    TC_TRY(cp(level, t->level.p, nn));
+    TC_TRY(cp(first, t->first.p, nn * 4));
+    TC_TRY(cp(count, t->count.p, nn * 4));
+    TC_TRY(cp(com, t->nx.p, nn * 24));
+    TC_TRY(cp(mass, t->nm.p, nn * 8));
+    return TC_OK;
+}
+
+tc_status tc_interaction_counts(const tc_tree* t, uint32_t* counts, void* stream)
+{
+    g_err.clear();
+    if (!t || !counts) return fail(TC_ERR_INVALID, "tc_interaction_counts: NULL argument");
+    if (!(t->state & 4u) || !t->counted) return fail(TC_ERR_STATE, "tc_interaction_counts: no counted tc_forces");
+    TC_TRY(check_device(t));
+    launch_scatter_counts(P<uint32_t>(t->sorted_counts), t->perm, t->n, counts, (hipStream_t)stream);
+    return check_launch("counts");
+}
+
+void tc_tree_free(tc_tree* t)
+{
+    if (!t) return;
+    (void)hipDeviceSynchronize();
+    Buf* bufs[] = {&t->keys0, &t->keys1, &t->vals0, &t->vals1, &t->sx, &t->sy, &t->sz, &t->sm, &t->c, &t->cnt,
+                   &t->pre, &t->sorted_counts, &t->diag_part, &t->sort_temp, &t->scan_temp, &t->bounds_part,
+                   &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->cs, &t->gidx, &t->parent,
+                   &t->list, &t->nm, &t->nx, &t->wn, &t->small};
+    for (Buf* b : bufs) release(t, *b);
+    for (auto& e : t->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (t->host) (void)hipHostFree(t->host);
+    delete t;
+}
+
+const char* tc_last_error(void) { return g_err.c_str(); }
+
+const char* tc_version(void) { return "treecode-gfx950 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal definitions shared by the HIP translation units of libtreecode.
+// Nothing here is part of the C ABI (include/treecode.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/treecode.h"
+
+namespace tc {
+
+constexpr int kMaxLevel = 21;          // 21 bits per axis, 63-bit keys
+constexpr int kLevels = kMaxLevel + 1;  // levels 0..21
+constexpr uint32_t kQMax = (1u << 21) - 1;
+
+// Root cube and input checks produced on the device by the bounds pass.
+struct Geom {
+    double lo[3];
+    double L;        // root side, a power of two
+    double scale;    // 2^21 / L (exact)
+    double h;        // L 2^-21, the finest cell side
+    int32_t log2L;
+    uint32_t bad;    // bit 0: non-finite position, bit 1: negative / non-finite mass
+    uint32_t nnodes; // filled by the build (node count read back to the host)
+    uint32_t pad;
+};
+
+// One node as the walk reads it.  Nodes are stored in "group order": the
+// root at 0, and the children of every internal node contiguous (octant
+// order), groups laid out in the pre-order of their parents.
+struct __align__(16) WalkNode {
+    double x, y, z;   // centre of mass
+    double m;         // total mass
+    uint32_t first;   // sorted index of the first particle
+    uint32_t count;   // particles in the node
+    uint32_t child;   // group index of the first child (internal nodes)
+    uint32_t meta;    // bits 0-3 nchild, bits 8-12 level, bit 16 leaf
+};
+static_assert(sizeof(WalkNode) == 48, "WalkNode layout");
+
+__host__ __device__ inline uint32_t meta_nchild(uint32_t m) { return m & 0xFu; }
+__host__ __device__ inline uint32_t meta_level(uint32_t m) { return (m >> 8) & 0x1Fu; }
+__host__ __device__ inline bool meta_leaf(uint32_t m) { return (m >> 16) & 1u; }
+
+// ---------------------------------------------------------------------------
+// launch wrappers (each defined next to its kernels)
+// ---------------------------------------------------------------------------
+
+// keys.hip
+void launch_bounds(const void* pos, const void* mass, int64_t n, tc_dtype dt, double* partials,
+                   int nblocks, Geom* geom, hipStream_t s);
+int bounds_blocks(int64_t n);
+void launch_keys(const void* pos, int64_t n, tc_dtype dt, const Geom* geom, uint64_t* keys,
+                 uint32_t* idx, hipStream_t s);
+void launch_gather(const void* pos, const void* mass, int64_t n, tc_dtype dt, const uint32_t* perm,
+                   double* sx, double* sy, double* sz, double* sm, hipStream_t s);
+
+// scan.hip: exclusive scan, out[n] = total (out has n+1 entries)
+size_t scan_temp_bytes(int64_t n);
+void launch_exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* temp,
+                               hipStream_t s);
+
+// sort.hip: stable LSD radix sort of (u64 key, u32 value) pairs over the
+// low `bits` key bits.  Result ends in (keys_out, vals_out); the *_alt
+// buffers are scratch.
+size_t radix_temp_bytes(int64_t n);
+void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                      int64_t n, int bits, void* temp, hipStream_t s, uint64_t** keys_out,
+                      uint32_t** vals_out);
+
+// build.hip
+void launch_adjacent_levels(const uint64_t* skeys, int64_t n, int8_t* c, hipStream_t s);
+void launch_node_counts(const int8_t* c, int64_t n, uint32_t* cnt, uint32_t* level_hist, hipStream_t s);
+void launch_emit_nodes(const uint64_t* skeys, const int8_t* c, const uint32_t* pre, int64_t n,
+                       uint8_t* level, uint32_t* first, uint32_t* count, uint32_t* next,
+                       hipStream_t s);
+void launch_count_children(const uint8_t* level, const uint32_t* count, const uint32_t* next,
+                           int64_t nn, uint32_t* nchild, hipStream_t s);
+void launch_assign_groups(const uint32_t* next, const uint32_t* nchild, const uint32_t* cs,
+                          int64_t nn, uint32_t* gidx, uint32_t* parent, hipStream_t s);
+void launch_level_lists(const uint8_t* level, int64_t nn, const uint32_t* level_off,
+                        uint32_t* cursor, uint32_t* list, hipStream_t s);
+
+// moments.hip (level_off_host: host copy of the per-level list offsets)
+void launch_moments(const uint32_t* first, const uint32_t* count, const uint32_t* next,
+                    const uint32_t* nchild, const uint32_t* cs, const uint32_t* gidx,
+                    const uint32_t* level_off_host, const uint32_t* list, const uint64_t* skeys,
+                    const double* sx, const double* sy, const double* sz, const double* sm,
+                    const Geom* geom, double* nm, double* nx, WalkNode* wn, hipStream_t s);
+
+// walk.hip
+struct WalkArgs {
+    const WalkNode* nodes;
+    const double* sx;
+    const double* sy;
+    const double* sz;
+    const double* sm;
+    const uint32_t* perm;
+    int64_t n;
+    double eps2;
+    double G;
+    double tau64[kLevels];  // (s_l / theta)^2, +inf for theta == 0
+    float tau32[kLevels];
+    void* acc;              // caller order, FP32 (F32C) or FP64 (F64)
+    void* pot;              // may be NULL
+    uint32_t* counts;       // sorted order (counting walk only)
+    double* diag;           // [waves, 4] partials of sum m a, sum m |a|
+    uint32_t* status;       // bit 0: stack overflow (never expected)
+};
+int64_t walk_waves(int64_t n);
+void launch_walk(const WalkArgs& a, tc_walk mode, bool count, hipStream_t s);
+
+// diag.hip
+void launch_diag_final(const double* part, int64_t nwaves, double* out4, hipStream_t s);
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+void launch_sum_counts(const uint32_t* counts, int64_t n, unsigned long long* out, hipStream_t s);
+void launch_scatter_counts(const uint32_t* sorted_counts, const uint32_t* perm, int64_t n,
+                           uint32_t* out, hipStream_t s);
+
+}  // namespace tc

@@ -1,0 +1,299 @@
+// The Barnes-Hut walk: accelerations and potentials of Eq.(1) with the
+// opening rule of the TreeCode description (section 2).
+//
+// Layout of the work.  One wavefront serves 64 consecutive targets in key
+// order (spatially compact).  It walks the union of the 64 lanes' open sets
+// depth first: a stack in LDS holds groups of sibling nodes together with the
+// 64-bit mask of lanes that opened their parent.  Popping a group stages its
+// <= 8 children into LDS (one lane per child); every active lane then applies
+// the exact per-particle rule to each child:
+//   - the node contains the target           -> open (never accepted);
+//   - |X - x|^2 > (s_l / theta)^2            -> accept: one monopole term;
+//   - otherwise                              -> open.
+// A ballot of the opening lanes decides whether the child's own group is
+// pushed.  A one-particle leaf gives the same term whether accepted or
+// opened, so it is taken directly (self excluded); a multi-particle leaf
+// (several particles sharing a level-21 cell) that is opened contributes its
+// particles one by one.  The interaction sets are therefore exactly those of
+// the per-particle algorithm; only the summation order differs.
+//
+// Precision.  F32C: node and target coordinates enter as FP32 offsets from a
+// per-wave FP64 anchor (the first target of the wave), formed in FP64 once
+// per staged node, so differences stay small and accurate; interactions are
+// FP32 (hardware reciprocal square root); each group's partial sums are added
+// into per-lane Kahan-compensated totals.  F64: absolute FP64 coordinates,
+// FP64 reciprocal square root refined by two Newton-Raphson steps, plain FP64
+// sums.  Both walks also reduce sum_i m_i a_i and sum_i m_i |a_i| in FP64,
+// one partial per wave, for the momentum diagnostic.
+#include <type_traits>
+
+#include "tc_internal.h"
+
+namespace tc {
+namespace {
+
+constexpr int kWalkWaves = 4;
+constexpr int kWalkThreads = 64 * kWalkWaves;
+// Pending groups never exceed 7 per level for levels 2..20 plus 8 at the
+// deepest level (<= 141); the bound below adds a margin.
+constexpr int kStack = 160;
+
+struct StackEntry {
+    uint32_t gs, nc, mlo, mhi;
+};
+
+struct __align__(16) Stg32 {
+    float x, y, z, m;
+    uint32_t first, count, child, meta;
+    float tau, p0, p1, p2;
+};
+
+struct __align__(16) Stg64 {
+    double x, y, z, m;
+    double tau, p0;
+    uint32_t first, count, child, meta;
+};
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// 1/sqrt(x) in FP64: hardware estimate refined by two Newton-Raphson steps
+// for f(y) = 1/y^2 - x, i.e. y <- y + y (1 - x y^2) / 2.
+__device__ inline double rsqrt64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+    r = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, r, y);
+    return y;
+}
+
+__device__ inline void kahan_add(float& s, float& c, float v)
+{
+    float y = v - c;
+    float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <typename R>
+__device__ inline R wave_sum(R v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <bool F64, bool COUNT>
+__global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
+{
+    using R = typename std::conditional<F64, double, float>::type;
+    using Stg = typename std::conditional<F64, Stg64, Stg32>::type;
+    __shared__ StackEntry stk[kWalkWaves][kStack];
+    __shared__ Stg stg[kWalkWaves][8];
+    __shared__ R tau_tab[kLevels];
+
+    if (threadIdx.x < kLevels) {
+        if constexpr (F64) tau_tab[threadIdx.x] = a.tau64[threadIdx.x];
+        else tau_tab[threadIdx.x] = a.tau32[threadIdx.x];
+    }
+    __syncthreads();
+
+    const int w = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63;
+    const int64_t wave_id = (int64_t)blockIdx.x * kWalkWaves + w;
+    const int64_t base = wave_id * 64;
+    if (base >= a.n) return;  // whole wave; no block barrier follows
+    const int64_t s = base + lane;
+    const bool valid = s < a.n;
+    const int64_t sl = valid ? s : base;
+    const uint32_t su = (uint32_t)s;
+
+    const double Ax = a.sx[base], Ay = a.sy[base], Az = a.sz[base];
+    const double xs = a.sx[sl], ys = a.sy[sl], zs = a.sz[sl];
+    R px, py, pz;
+    if constexpr (F64) {
+        px = xs; py = ys; pz = zs;
+    } else {
+        px = (float)(xs - Ax); py = (float)(ys - Ay); pz = (float)(zs - Az);
+    }
+    const R eps2 = (R)a.eps2;
+
+    // running totals: F32C keeps (sum, compensation) pairs
+    R tx = 0, ty = 0, tz = 0, tp = 0;
+    float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
+    uint32_t nint = 0;
+
+    int sp = 0;
+    const uint64_t vmask = __ballot(valid);
+    {
+        const uint32_t rmeta = uni(a.nodes[0].meta);
+        const uint32_t rchild = uni(a.nodes[0].child);
+        if (!meta_leaf(rmeta)) {
+            if (lane == 0) stk[w][0] = StackEntry{rchild, meta_nchild(rmeta), (uint32_t)vmask, (uint32_t)(vmask >> 32)};
+            sp = 1;
+        }
+    }
+    wave_sync();
+
+    while (sp > 0) {
+        --sp;
+        const StackEntry e = stk[w][sp];
+        const uint32_t gs = uni(e.gs);
+        uint32_t nc = uni(e.nc);
+        if (nc > 8) {  // impossible in an octree; keeps the staging in bounds
+            if (lane == 0) atomicOr(a.status, 2u);
+            nc = 8;
+        }
+        const uint64_t mask = ((uint64_t)uni(e.mhi) << 32) | uni(e.mlo);
+        if (lane < nc) {
+            const WalkNode nd = a.nodes[gs + lane];
+            Stg st;
+            const bool single = meta_leaf(nd.meta) && nd.count == 1;
+            if constexpr (F64) {
+                st.x = nd.x; st.y = nd.y; st.z = nd.z; st.m = nd.m;
+            } else {
+                st.x = (float)(nd.x - Ax); st.y = (float)(nd.y - Ay); st.z = (float)(nd.z - Az);
+                st.m = (float)nd.m;
+            }
+            st.tau = single ? (R)-1 : tau_tab[meta_level(nd.meta)];
+            st.first = nd.first;
+            st.count = nd.count;
+            st.child = nd.child;
+            st.meta = nd.meta;
+            stg[w][lane] = st;
+        }
+        wave_sync();
+
+        const bool act = (mask >> lane) & 1ull;
+        R bx = 0, by = 0, bz = 0, bp = 0;
+        for (uint32_t k = 0; k < nc; ++k) {
+            const R X = stg[w][k].x, Y = stg[w][k].y, Z = stg[w][k].z, M = stg[w][k].m;
+            const R tau = stg[w][k].tau;
+            const uint32_t f = uni(stg[w][k].first), cnt = uni(stg[w][k].count);
+            const R dx = X - px, dy = Y - py, dz = Z - pz;
+            const R d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const bool inside = (su - f) < cnt;
+            const bool accept = act && !inside && d2 > tau;
+            if (accept) {
+                R ri;
+                if constexpr (F64) ri = rsqrt64(d2 + eps2);
+                else ri = __builtin_amdgcn_rsqf(d2 + eps2);
+                const R mr = M * ri;
+                const R mr3 = mr * ri * ri;
+                bx = fma(mr3, dx, bx);
+                by = fma(mr3, dy, by);
+                bz = fma(mr3, dz, bz);
+                bp -= mr;
+                if constexpr (COUNT) ++nint;
+            }
+            const bool open = act && !accept && !(tau < (R)0);
+            const uint64_t om = __ballot(open);
+            if (om) {
+                const uint32_t meta = uni(stg[w][k].meta);
+                if (!meta_leaf(meta)) {
+                    const uint32_t child = uni(stg[w][k].child);
+                    if (sp < kStack) {
+                        if (lane == 0) stk[w][sp] = StackEntry{child, meta_nchild(meta), (uint32_t)om, (uint32_t)(om >> 32)};
+                        ++sp;
+                    } else if (lane == 0) {
+                        atomicOr(a.status, 1u);
+                    }
+                } else {
+                    // particles of a multi-particle leaf, one by one (j != target)
+                    for (uint32_t j = f; j < f + cnt; ++j) {
+                        const double xj = a.sx[j], yj = a.sy[j], zj = a.sz[j];
+                        const R mj = (R)a.sm[j];
+                        if (open && j != su) {
+                            R ex, ey, ez;
+                            if constexpr (F64) {
+                                ex = xj - xs; ey = yj - ys; ez = zj - zs;
+                            } else {
+                                ex = (float)(xj - Ax) - px; ey = (float)(yj - Ay) - py; ez = (float)(zj - Az) - pz;
+                            }
+                            const R q = fma(ex, ex, fma(ey, ey, ez * ez)) + eps2;
+                            R ri;
+                            if constexpr (F64) ri = rsqrt64(q);
+                            else ri = __builtin_amdgcn_rsqf(q);
+                            const R mr = mj * ri;
+                            const R mr3 = mr * ri * ri;
+                            bx = fma(mr3, ex, bx);
+                            by = fma(mr3, ey, by);
+                            bz = fma(mr3, ez, bz);
+                            bp -= mr;
+                            if constexpr (COUNT) ++nint;
+                        }
+                    }
+                }
+            }
+        }
+        wave_sync();
+        if constexpr (F64) {
+            tx += bx; ty += by; tz += bz; tp += bp;
+        } else {
+            kahan_add(tx, cx, bx);
+            kahan_add(ty, cy, by);
+            kahan_add(tz, cz, bz);
+            kahan_add(tp, cp, bp);
+        }
+    }
+
+    R ox, oy, oz, op;
+    if constexpr (F64) {
+        ox = tx; oy = ty; oz = tz; op = tp;
+    } else {
+        ox = tx - cx; oy = ty - cy; oz = tz - cz; op = tp - cp;
+    }
+    const R G = (R)a.G;
+    ox *= G; oy *= G; oz *= G; op *= G;
+
+    double dm[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+        const uint32_t i = a.perm[s];
+        R* acc = (R*)a.acc;
+        acc[3 * (int64_t)i + 0] = ox;
+        acc[3 * (int64_t)i + 1] = oy;
+        acc[3 * (int64_t)i + 2] = oz;
+        if (a.pot) ((R*)a.pot)[i] = op;
+        if constexpr (COUNT) a.counts[s] = nint;
+        const double m = a.sm[s];
+        const double ex = (double)ox, ey = (double)oy, ez = (double)oz;
+        dm[0] = m * ex;
+        dm[1] = m * ey;
+        dm[2] = m * ez;
+        dm[3] = m * sqrt(ex * ex + ey * ey + ez * ez);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dm[k] = wave_sum(dm[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a.diag[4 * wave_id + k] = dm[k];
+    }
+}
+
+}  // namespace
+
+int64_t walk_waves(int64_t n) { return (n + 63) / 64; }
+
+void launch_walk(const WalkArgs& a, tc_walk mode, bool count, hipStream_t s)
+{
+    if (a.n == 0) return;
+    const int64_t waves = walk_waves(a.n);
+    const unsigned blocks = (unsigned)((waves + kWalkWaves - 1) / kWalkWaves);
+    if (mode == TC_WALK_F64) {
+        if (count) k_walk<true, true><<<blocks, kWalkThreads, 0, s>>>(a);
+        else k_walk<true, false><<<blocks, kWalkThreads, 0, s>>>(a);
+    } else {
+        if (count) k_walk<false, true><<<blocks, kWalkThreads, 0, s>>>(a);
+        else k_walk<false, false><<<blocks, kWalkThreads, 0, s>>>(a);
+    }
+}
+
+}  // namespace tc

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (stated where they are asserted):
+  * keys, permutation, node table (level, first, count): bit-exact;
+  * FP64 moments: bit-exact (same summation order, no FMA contraction);
+  * accelerations, F32C walk: median relative error <= 1e-5, p99 <= 1e-4;
+  * accelerations, F64 walk: median <= 1e-13, p99 <= 1e-11;
+  * interaction counts: F64 equal to the oracle's; F32C may differ only for
+    targets where a distance sits within FP32 rounding of the opening
+    threshold, required on < 1% of targets.
+Inputs are seeded (workloads); sizes span several sort tiles (4096), walk
+waves (64) and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _tc():
+    import paper_2412_01733_amd as tc
+    return tc
+
+
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def gpu_run(pos, mass, theta, eps, G=1.0, walk="f32c", count=True):
+    tc = _tc()
+    p = torch.from_numpy(np.ascontiguousarray(pos)).to(dev())
+    m = torch.from_numpy(np.ascontiguousarray(mass)).to(dev())
+    acc, pot, tree = tc.forces(p, m, theta, eps, G, walk=walk, count=count)
+    torch.cuda.synchronize()
+    out = dict(acc=acc.cpu().double().numpy(), pot=pot.cpu().double().numpy(), tree=tree)
+    if count:
+        out["counts"] = tree.interaction_counts().cpu().numpy().astype(np.int64)
+    return out
+
+
+def rel_err(a, b):
+    return np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)
+
+
+def check_forces(g, acc, pot, walk):
+    e = rel_err(g["acc"], acc)
+    ep = np.abs(g["pot"] - pot) / np.abs(pot)
+    if walk == "f32c":
+        med, p99 = 1e-5, 1e-4
+    else:
+        med, p99 = 1e-13, 1e-11
+    assert np.median(e) <= med and np.quantile(e, 0.99) <= p99, (np.median(e), np.quantile(e, 0.99))
+    assert np.median(ep) <= med and np.quantile(ep, 0.99) <= p99, (np.median(ep), np.quantile(ep, 0.99))
+    return e
+
+
+def check_tree(tree, T, moments=True):
+    ex = {k: v.cpu().numpy() for k, v in tree.export(moments=moments).items()}
+    ok, op = T.sorted()
+    nd = T.nodes()
+    assert (ex["keys"].view(np.uint64) == ok).all(), "keys differ"
+    assert (ex["perm"].astype(np.int64) == op).all(), "permutation differs"
+    assert len(ex["level"]) == len(nd["level"]), "node count differs"
+    assert (ex["level"].astype(np.int32) == nd["level"]).all()
+    assert (ex["first"].astype(np.int64) == nd["first"]).all()
+    assert (ex["count"].astype(np.int64) == nd["count"]).all()
+    if moments:
+        assert (ex["mass"] == nd["mass"]).all(), "moments (mass) not bit-exact"
+        assert (ex["com"] == nd["com"]).all(), "moments (com) not bit-exact"
+
+
+def _dups(n, seed):
+    g = np.random.default_rng(seed)
+    pos = g.random((n, 3))
+    pos[n // 3:n // 3 + 7] = pos[0]
+    pos[n // 2:n // 2 + 3] = pos[5] + 1e-9
+    return pos
+
+
+CASES = [
+    ("plummer16k_f64", lambda: workloads.plummer(16384, 1000), 0.7, 0.01),
+    ("plummer5000_f32", lambda: workloads.plummer(5000, 3, dtype=np.float32), 0.5, 0.01),
+    ("dups4097_f64", lambda: (_dups(4097, 4), np.full(4097, 1.0 / 4097)), 0.6, 0.001),
+]
+
+
+@pytest.mark.parametrize("name,make,theta,eps", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("walk", ["f32c", "f64"])
+def test_tree_and_forces_match_oracle(name, make, theta, eps, walk):
+    pos, m = make()
+    print("case", name, walk, flush=True)
+    g = gpu_run(pos, m, theta, eps, walk=walk)
+    T = oracle.Tree(pos, m)
+    check_tree(g["tree"], T)
+    acc, pot, nint = T.forces(theta, eps)
+    check_forces(g, acc, pot, walk)
+    flips = np.mean(g["counts"] != nint)
+    if walk == "f64":
+        assert flips <= 1e-3, flips
+    else:
+        assert flips < 0.01, flips
+    st = g["tree"].stats()
+    assert st["interactions"] == int(g["counts"].sum())
+
+
+@pytest.mark.parametrize("walk", ["f32c", "f64"])
+def test_theta_zero_is_direct_sum(walk):
+    pos, m = workloads.plummer(3000, 77)
+    g = gpu_run(pos, m, 0.0, 0.01, walk=walk)
+    ad, pd = oracle.direct(pos, m, 0.01)
+    check_forces(g, ad, pd, walk)
+    assert (g["counts"] == 2999).all()
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 63, 64, 65, 4095, 4096, 4097])
+def test_small_and_ragged_sizes(n):
+    pos, m = workloads.plummer(max(n, 1), 900 + n)
+    pos, m = pos[:n], m[:n]
+    tc = _tc()
+    p = torch.from_numpy(pos).to(dev())
+    mm = torch.from_numpy(m).to(dev())
+    acc, pot, tree = tc.forces(p, mm, 0.6, 0.05, walk="f64")
+    torch.cuda.synchronize()
+    assert acc.shape == (n, 3)
+    if n == 0:
+        return
+    T = oracle.Tree(pos, m)
+    check_tree(tree, T)
+    a, ph, _ = T.forces(0.6, 0.05)
+    if n == 1:
+        assert (acc.cpu().numpy() == 0).all() and (pot.cpu().numpy() == 0).all()
+    else:
+        g = dict(acc=acc.cpu().numpy(), pot=pot.cpu().numpy())
+        check_forces(g, a, ph, "f64")
+
+
+def test_two_body_closed_form():
+    x = np.array([[0.0, 0.0, 0.0], [3.0, 4.0, 0.0]])
+    m = np.array([2.0, 5.0])
+    eps, G = 0.5, 1.5
+    q = 25.0 + eps * eps
+    for walk in ("f64", "f32c"):
+        for theta in (0.0, 0.5, 10.0):
+            g = gpu_run(x, m, theta, eps, G, walk=walk)
+            want = np.array([G * 5.0 * np.array([3.0, 4.0, 0.0]) / q ** 1.5,
+                             -G * 2.0 * np.array([3.0, 4.0, 0.0]) / q ** 1.5])
+            tol = 1e-15 if walk == "f64" else 3e-7
+            assert np.abs(g["acc"] - want).max() <= tol * np.abs(want).max()
+            assert np.allclose(g["pot"], [-G * 5.0 / q ** 0.5, -G * 2.0 / q ** 0.5], rtol=tol, atol=0)
+
+
+def test_determinism_bitwise():
+    pos, m = workloads.plummer(20000, 5, dtype=np.float32)
+    a = gpu_run(pos, m, 0.5, 0.01)
+    b = gpu_run(pos, m, 0.5, 0.01)
+    assert (a["acc"] == b["acc"]).all() and (a["pot"] == b["pot"]).all()
+    assert (a["counts"] == b["counts"]).all()
+
+
+def test_momentum_diagnostic_matches_oracle():
+    pos, m = workloads.plummer(30000, 6, dtype=np.float32)
+    for walk in ("f32c", "f64"):
+        g = gpu_run(pos, m, 0.5, 0.01, walk=walk)
+        acc, _, _ = oracle.forces(pos, m, 0.5, 0.01)
+        md = m.astype(np.float64)
+        P = (md[:, None] * acc).sum(0)
+        S = (md * np.linalg.norm(acc, axis=1)).sum()
+        st = g["tree"].stats()
+        Pg = np.array(st["momentum"])
+        assert abs(st["sum_m_abs_a"] / S - 1) < 1e-6
+        assert abs(np.linalg.norm(Pg) / st["sum_m_abs_a"] - np.linalg.norm(P) / S) <= 1e-6
+
+
+def test_power_of_two_scaling():
+    pos, m = workloads.plummer(8000, 8)
+    g1 = gpu_run(pos, m, 0.6, 0.01, walk="f64")
+    g2 = gpu_run(pos * 0.25, m, 0.6, 0.0025, walk="f64")
+    k1 = g1["tree"].export(moments=False)["keys"].cpu().numpy()
+    k2 = g2["tree"].export(moments=False)["keys"].cpu().numpy()
+    assert (k1 == k2).all()
+    assert (g1["counts"] == g2["counts"]).all()
+    assert np.abs(g2["acc"] / 16.0 - g1["acc"]).max() <= 1e-14 * np.abs(g1["acc"]).max()
+
+
+def test_invalid_input_reported():
+    tc = _tc()
+    from paper_2412_01733_amd._lib import TreecodeError, TC_ERR_INPUT, TC_ERR_INVALID, TC_ERR_STATE
+    pos = torch.zeros((10, 3), dtype=torch.float32, device=dev())
+    pos[3, 1] = float("nan")
+    m = torch.ones(10, dtype=torch.float32, device=dev())
+    t = tc.Tree()
+    with pytest.raises(TreecodeError) as ei:
+        t.build(pos, m)
+    assert ei.value.status == TC_ERR_INPUT
+    pos[3, 1] = 0.0
+    m[2] = -1.0
+    with pytest.raises(TreecodeError) as ei:
+        t.build(pos, m)
+    assert ei.value.status == TC_ERR_INPUT
+    m[2] = 1.0
+    t.build(pos, m)
+    with pytest.raises(TreecodeError) as ei:
+        t.forces(0.5, 0.01)
+    assert ei.value.status == TC_ERR_STATE
+    t.moments()
+    with pytest.raises(TreecodeError) as ei:
+        t.forces(-0.5, 0.01)
+    assert ei.value.status == TC_ERR_INVALID
+
+
+def test_tree_reuse_grows_and_shrinks():
+    tc = _tc()
+    t = tc.Tree()
+    for n, seed in ((5000, 1), (20000, 2), (300, 3)):
+        pos, m = workloads.plummer(n, seed, dtype=np.float32)
+        p = torch.from_numpy(pos).to(dev())
+        mm = torch.from_numpy(m).to(dev())
+        acc, pot, _ = tc.forces(p, mm, 0.5, 0.01, tree=t)
+        torch.cuda.synchronize()
+        a, ph, _ = oracle.forces(pos, m, 0.5, 0.01)
+        check_forces(dict(acc=acc.cpu().double().numpy(), pot=pot.cpu().double().numpy()), a, ph, "f32c")
