@@ -1,0 +1,225 @@
+"""Benchmark: TreeCode force evaluation on one MI355X.
+
+Workload (default): Plummer sphere, N = 1e7, FP32 positions and masses,
+theta = 0.5, eps = 0.005, G = 1 (seed 1002).  One step = the whole hot path
+through the C ABI: root cube + Morton keys, radix sort, octree build, upward
+moments, Barnes-Hut walk, unsort and FP64 momentum diagnostic (tc_build +
+tc_moments + tc_forces).  The headline is particle-forces/s = N / step time
+for the compensated-FP32 walk; the plain-FP64 walk is timed the same way and
+reported beside it, each with its error against the FP64 oracle on a seeded
+sample of targets.
+
+Prints one JSON line.  Options:
+  --gpus N        only 1 is supported (one GPU per run)
+  --steps K       timed steps per walk (default 10)
+  --warmup W      untimed steps per walk (default 3)
+  --no-cpu        skip the oracle leg (CPU baseline + accuracy)
+  --calib-copy    also run a device copy of 1 GiB (calibrates rocprofv3 byte counters)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOPS_PER_INTERACTION = 20          # acc + pot, rsqrt counted as one
+PEAK_FP32_TFLOPS = 157.3             # MI355X FP32 vector (packed FMA)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6    # one FMA per lane per clock: 256 CU x 64 lanes x 2 x 2.4 GHz
+PEAK_FP64_TFLOPS = 78.6
+
+
+def sem(x):
+    x = np.asarray(x, np.float64)
+    if len(x) < 2:
+        return 0.0
+    return float(np.sqrt(((x - x.mean()) ** 2).sum() / (len(x) * (len(x) - 1))))
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--eps", type=float, default=0.005)
+    ap.add_argument("--seed", type=int, default=1002)
+    ap.add_argument("--walks", default="f32c,f64")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 18)
+    ap.add_argument("--acc-sample", type=int, default=1 << 16)
+    ap.add_argument("--calib-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the TreeCode path here is a single-GPU build "
+              "(see DESIGN.md for how it would shard); --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2412_01733_amd as tc
+    import workloads
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    log("bench: generating Plummer N=%d seed=%d" % (n, args.seed))
+    pos_np, m_np = workloads.plummer(n, args.seed, dtype=np.float32)
+    pos = torch.from_numpy(pos_np).to(dev)
+    mass = torch.from_numpy(m_np).to(dev)
+    torch.cuda.synchronize()
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    tree = tc.Tree()
+    walks = [w for w in args.walks.split(",") if w]
+    res = {}
+    for walk in walks:
+        dt = torch.float32 if walk == "f32c" else torch.float64
+        acc = torch.empty((n, 3), dtype=dt, device=dev)
+        pot = torch.empty((n,), dtype=dt, device=dev)
+
+        def step():
+            tree.build(pos, mass)
+            tree.moments()
+            tree.forces(args.theta, args.eps, walk=walk, out=(acc, pot))
+
+        # counted pass: the interaction total (the algorithmic work) of this walk
+        tree.set_timing(False)
+        tree.build(pos, mass).moments()
+        tree.forces(args.theta, args.eps, walk=walk, count=True, out=(acc, pot))
+        st = tree.stats()
+        inter = st["interactions"]
+        n_nodes = st["n_nodes"]
+        util = dict(active=inter / max(st["lane_visits"], 1), all=inter / max(64 * st["node_visits"], 1),
+                    node_visits=st["node_visits"], leaves=st["n_leaves"], multi_leaves=st["n_multi_leaves"])
+        log("bench: %s interactions %d (%.1f per target), nodes %d" % (walk, inter, inter / n, n_nodes))
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        tree.set_timing(True)
+        stage = []
+        step_ms = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s0 = time.perf_counter()
+            step()
+            st = tree.stats()  # synchronises the stream and reads this step's stage events
+            step_ms.append((time.perf_counter() - s0) * 1e3)
+            stage.append(st["stage_ms"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tree.set_timing(False)
+        total_ms = (t1 - t0) * 1e3 / args.steps
+        stage = np.array(stage)
+        walk_ms = stage[:, 4]
+        res[walk] = dict(
+            ms_per_step=total_ms, ms_per_step_sem=sem(step_ms),
+            value=n / (total_ms * 1e-3),
+            walk_ms=float(walk_ms.mean()), walk_ms_sem=sem(walk_ms),
+            stage_ms={k: round(float(stage[:, i].mean()), 4) for i, k in
+                      enumerate(["keys", "sort", "tree", "moments", "walk", "diag"])},
+            interactions=int(inter), n_nodes=int(n_nodes), util=util,
+            momentum_ratio=float(np.linalg.norm(st["momentum"]) / st["sum_m_abs_a"]),
+            acc=acc, pot=pot,
+        )
+        log("bench: %s step %.3f ms (walk %.3f ms) -> %.4g particle-forces/s" %
+            (walk, total_ms, walk_ms.mean(), n / (total_ms * 1e-3)))
+
+    out_acc = {}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        nthreads = max(1, min(16, os.cpu_count() or 1))
+        log("bench: oracle build at full N (1 thread) ...")
+        tb0 = time.perf_counter()
+        T = oracle.Tree(pos_np, m_np)
+        t_build = time.perf_counter() - tb0
+        tg = workloads.target_sample(n, args.cpu_sample, 2002)
+        log("bench: oracle walk on %d sampled targets (%d threads) ..." % (len(tg), nthreads))
+        tw0 = time.perf_counter()
+        ra, rp, rn = T.forces(args.theta, args.eps, targets=tg, nthreads=nthreads)
+        t_walk = time.perf_counter() - tw0
+        t_full = t_build + t_walk * n / len(tg)
+        cpu = dict(value=n / t_full, unit="particle-forces/s", cores=nthreads, kind="oracle",
+                   sample="full-N build (1 thread, %.2f s) + walk of %d seeded targets (%d threads, %.2f s), "
+                          "extrapolated to N" % (t_build, len(tg), nthreads, t_walk))
+        k = min(args.acc_sample, len(tg))
+        sel = tg[:k]
+        for walk in walks:
+            a = res[walk]["acc"][torch.from_numpy(sel).to(dev)].double().cpu().numpy()
+            p = res[walk]["pot"][torch.from_numpy(sel).to(dev)].double().cpu().numpy()
+            e = np.linalg.norm(a - ra[:k], axis=1) / np.linalg.norm(ra[:k], axis=1)
+            ep = np.abs(p - rp[:k]) / np.abs(rp[:k])
+            out_acc[walk] = dict(median=float(np.median(e)), p99=float(np.quantile(e, 0.99)),
+                                 pot_median=float(np.median(ep)), pot_p99=float(np.quantile(ep, 0.99)),
+                                 targets=int(k))
+        oracle_inter = int(rn.sum())
+        cpu["oracle_interactions_per_target"] = oracle_inter / len(tg)
+
+    head = walks[0]
+    r = res[head]
+    flops = FLOPS_PER_INTERACTION * r["interactions"]
+    achieved = flops / (r["walk_ms"] * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if head == "f32c" else PEAK_FP64_TFLOPS
+    line = {
+        "metric": "particle-forces/sec at N=1e7, theta=0.5 (FP32 vs FP64 walk); fwd+adjoint ms",
+        "value": r["value"],
+        "unit": "particle-forces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "f32c" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "plummer-N%d-theta%g-eps%g" % (n, args.theta, args.eps), "n": n,
+                   "theta": args.theta, "eps": args.eps, "walk": head, "inputs": "fp32, seed %d" % args.seed},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_walk<%s>" % ("F32C" if head == "f32c" else "F64"),
+                     "flops_per_interaction": FLOPS_PER_INTERACTION, "interactions": r["interactions"],
+                     "walk_ms": r["walk_ms"],
+                     "frac_nonpacked_fp32": (achieved / PEAK_FP32_NONPACKED_TFLOPS) if head == "f32c" else None},
+        "cpu_baseline": cpu,
+        "walks": {},
+        "accuracy_vs_oracle": out_acc,
+    }
+    for walk in walks:
+        rr = res[walk]
+        fl = FLOPS_PER_INTERACTION * rr["interactions"] / (rr["walk_ms"] * 1e-3) / 1e12
+        line["walks"][walk] = dict(
+            value=rr["value"], ms_per_step=rr["ms_per_step"], ms_per_step_sem=rr["ms_per_step_sem"],
+            walk_ms=rr["walk_ms"], walk_ms_sem=rr["walk_ms_sem"], walk_only_rate=n / (rr["walk_ms"] * 1e-3),
+            walk_tflops=fl, stage_ms=rr["stage_ms"], interactions=rr["interactions"],
+            interactions_per_target=rr["interactions"] / n, n_nodes=rr["n_nodes"],
+            lane_utilisation=rr["util"],
+            momentum_ratio=rr["momentum_ratio"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

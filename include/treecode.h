@@ -138,6 +138,8 @@ typedef struct {
     uint32_t state;          /* bit 0 built, bit 1 moments, bit 2 forces */
     uint32_t last_mode;      /* tc_walk of the last tc_forces */
     uint64_t interactions;   /* sum over targets of the interaction count (TC_COUNT), else 0 */
+    uint64_t node_visits;    /* TC_COUNT: node evaluations summed over wavefronts (64 targets each) */
+    uint64_t lane_visits;    /* TC_COUNT: the same weighted by the lanes active at each evaluation */
     double momentum[3];      /* sum_i m_i a_i of the last tc_forces (FP64) */
     double sum_m_abs_a;      /* sum_i m_i |a_i| (FP64) */
     float stage_ms[8];       /* last timed durations: 0 keys, 1 sort, 2 tree, 3 moments,

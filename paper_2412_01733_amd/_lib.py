@@ -37,6 +37,8 @@ class TcStats(ctypes.Structure):
         ("state", ctypes.c_uint32),
         ("last_mode", ctypes.c_uint32),
         ("interactions", ctypes.c_uint64),
+        ("node_visits", ctypes.c_uint64),
+        ("lane_visits", ctypes.c_uint64),
         ("momentum", ctypes.c_double * 3),
         ("sum_m_abs_a", ctypes.c_double),
         ("stage_ms", ctypes.c_float * 8),

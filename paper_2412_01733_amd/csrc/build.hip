@@ -15,9 +15,11 @@
 // A node's end is found by galloping search on the keys, and its skip link
 // ("next") is the pre-order index of the first node starting at its end.
 //
-// The walk wants siblings contiguous, so a second numbering ("group order")
-// places the root at 0 and the children of internal node p at
-// 1 + (number of children of all internal nodes before p in pre-order).
+// The walk wants siblings contiguous and the upward pass wants each level
+// contiguous, so the walk's node array is in breadth-first order: sorted by
+// (level, first), obtained by one stable 8-bit radix pass on the level of
+// the pre-order nodes.  The children of pre-order node p then start at the
+// breadth-first index of p + 1 and are consecutive.
 #include "tc_internal.h"
 
 namespace tc {
@@ -53,25 +55,46 @@ __device__ inline void node_range(const int8_t* c, int64_t s, int& lo, int& hi)
     hi = m + 1 < kMaxLevel ? m + 1 : kMaxLevel;
 }
 
-// Node count per first particle, plus a histogram of node levels.
+// Node count per first particle, plus a histogram of node levels and the
+// leaf counts (counted per wave with ballots, then one atomic per entry and
+// block).  hist[0..21]: nodes per level; hist[22]: leaves; hist[23]:
+// multi-particle leaves.  The deepest node starting at s is always a leaf,
+// and it holds several particles iff it sits at level 21 and s + 1 shares it.
 __global__ __launch_bounds__(256) void k_node_counts(const int8_t* __restrict__ c, int64_t n,
                                                      uint32_t* __restrict__ cnt,
                                                      uint32_t* __restrict__ level_hist)
 {
-    __shared__ uint32_t h[kLevels];
-    if (threadIdx.x < kLevels) h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n) {
-        int lo, hi;
-        node_range(c, s, lo, hi);
-        int k = hi - lo + 1;
-        if (k < 0) k = 0;
-        cnt[s] = (uint32_t)k;
-        for (int l = lo; l <= hi; ++l) atomicAdd(&h[l], 1u);
+    constexpr int kH = kLevels + 2;
+    __shared__ uint32_t h[256 / 64][kH];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t acc = 0;  // lane l < kH of each wave accumulates entry l
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t s0 = start - threadIdx.x; s0 < n; s0 += stride) {
+        const int64_t s = s0 + threadIdx.x;
+        int lo = 1, hi = 0, cs = -1;
+        if (s < n) {
+            node_range(c, s, lo, hi);
+            cs = (int)c[s];
+            int k = hi - lo + 1;
+            cnt[s] = (uint32_t)(k > 0 ? k : 0);
+        }
+        for (int l = 0; l < kLevels; ++l) {
+            const uint32_t b = (uint32_t)__popcll(__ballot(lo <= l && l <= hi));
+            if (lane == l) acc += b;
+        }
+        const uint32_t bl = (uint32_t)__popcll(__ballot(lo <= hi));
+        const uint32_t bm = (uint32_t)__popcll(__ballot(lo <= hi && hi == kMaxLevel && cs == kMaxLevel));
+        if (lane == kLevels) acc += bl;
+        if (lane == kLevels + 1) acc += bm;
     }
+    if (lane < kH) h[w][lane] = acc;
     __syncthreads();
-    if (threadIdx.x < kLevels && h[threadIdx.x]) atomicAdd(&level_hist[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < kH) {
+        uint32_t t = 0;
+        for (int ww = 0; ww < 256 / 64; ++ww) t += h[ww][threadIdx.x];
+        if (t) atomicAdd(&level_hist[threadIdx.x], t);
+    }
 }
 
 // First index j > s whose level-l prefix differs from that of key (or n).
@@ -120,6 +143,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ k, co
 
 __device__ inline bool is_internal(uint8_t level, uint32_t count) { return count >= 2 && level < kMaxLevel; }
 
+// Children per node, walked through the skip links.
 __global__ __launch_bounds__(256) void k_count_children(const uint8_t* __restrict__ level,
                                                         const uint32_t* __restrict__ count,
                                                         const uint32_t* __restrict__ next, int64_t nn,
@@ -139,49 +163,22 @@ __global__ __launch_bounds__(256) void k_count_children(const uint8_t* __restric
     nchild[p] = k;
 }
 
-__global__ __launch_bounds__(256) void k_assign_groups(const uint32_t* __restrict__ next,
-                                                       const uint32_t* __restrict__ nchild,
-                                                       const uint32_t* __restrict__ cs, int64_t nn,
-                                                       uint32_t* __restrict__ gidx,
-                                                       uint32_t* __restrict__ parent)
+// Sort input for the breadth-first permutation: key = level, value = p.
+__global__ __launch_bounds__(256) void k_level_keys(const uint8_t* __restrict__ level, int64_t nn,
+                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nn) return;
-    if (p == 0) {
-        gidx[0] = 0;
-        parent[0] = 0xFFFFFFFFu;
-    }
-    const uint32_t nc = nchild[p];
-    uint32_t ch = (uint32_t)p + 1;
-    const uint32_t base = 1 + cs[p];
-    for (uint32_t k = 0; k < nc; ++k) {
-        gidx[ch] = base + k;
-        parent[ch] = (uint32_t)p;
-        ch = next[ch];
-    }
+    keys[p] = level[p];
+    vals[p] = (uint32_t)p;
 }
 
-// Per-level node lists (order inside a level is irrelevant to the results).
-__global__ __launch_bounds__(256) void k_level_lists(const uint8_t* __restrict__ level, int64_t nn,
-                                                     const uint32_t* __restrict__ off,
-                                                     uint32_t* __restrict__ cursor,
-                                                     uint32_t* __restrict__ list)
+__global__ __launch_bounds__(256) void k_bfs_scatter(const uint32_t* __restrict__ bfs_to_pre, int64_t nn,
+                                                     uint32_t* __restrict__ bfs)
 {
-    __shared__ uint32_t h[kLevels];
-    __shared__ uint32_t hb[kLevels];
-    if (threadIdx.x < kLevels) h[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int l = -1;
-    uint32_t r = 0;
-    if (p < nn) {
-        l = level[p];
-        r = atomicAdd(&h[l], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < kLevels) hb[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]) : 0u;
-    __syncthreads();
-    if (p < nn) list[off[l] + hb[l] + r] = (uint32_t)p;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nn) return;
+    bfs[bfs_to_pre[b]] = (uint32_t)b;
 }
 
 }  // namespace
@@ -195,7 +192,9 @@ void launch_adjacent_levels(const uint64_t* skeys, int64_t n, int8_t* c, hipStre
 void launch_node_counts(const int8_t* c, int64_t n, uint32_t* cnt, uint32_t* level_hist, hipStream_t s)
 {
     if (n == 0) return;
-    k_node_counts<<<grid_for(n, 256), 256, 0, s>>>(c, n, cnt, level_hist);
+    unsigned b = grid_for(n, 256);
+    if (b > 1024) b = 1024;
+    k_node_counts<<<b, 256, 0, s>>>(c, n, cnt, level_hist);
 }
 
 void launch_emit_nodes(const uint64_t* skeys, const int8_t* c, const uint32_t* pre, int64_t n,
@@ -212,18 +211,14 @@ void launch_count_children(const uint8_t* level, const uint32_t* count, const ui
     k_count_children<<<grid_for(nn, 256), 256, 0, s>>>(level, count, next, nn, nchild);
 }
 
-void launch_assign_groups(const uint32_t* next, const uint32_t* nchild, const uint32_t* cs, int64_t nn,
-                          uint32_t* gidx, uint32_t* parent, hipStream_t s)
+void launch_bfs_order(const uint8_t* level, int64_t nn, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                      void* sort_temp, uint32_t* bfs, uint32_t** bfs_to_pre, hipStream_t s)
 {
     if (nn == 0) return;
-    k_assign_groups<<<grid_for(nn, 256), 256, 0, s>>>(next, nchild, cs, nn, gidx, parent);
-}
-
-void launch_level_lists(const uint8_t* level, int64_t nn, const uint32_t* level_off, uint32_t* cursor,
-                        uint32_t* list, hipStream_t s)
-{
-    if (nn == 0) return;
-    k_level_lists<<<grid_for(nn, 256), 256, 0, s>>>(level, nn, level_off, cursor, list);
+    k_level_keys<<<grid_for(nn, 256), 256, 0, s>>>(level, nn, k0, v0);
+    uint64_t* ko;
+    radix_sort_pairs(k0, v0, k1, v1, nn, 8, sort_temp, s, &ko, bfs_to_pre);
+    k_bfs_scatter<<<grid_for(nn, 256), 256, 0, s>>>(*bfs_to_pre, nn, bfs);
 }
 
 }  // namespace tc

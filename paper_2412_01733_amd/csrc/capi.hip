@@ -53,11 +53,12 @@ enum Stage { kStKeys = 0, kStSort, kStTree, kStMoments, kStWalk, kStDiag, kStBwd
 
 struct HostMirror {
     Geom geom;
-    uint32_t level_hist[kLevels];
+    uint32_t level_hist[kLevels + 2];
     uint32_t total;
     uint32_t level_off[kLevels + 1];
     double diag[4];
     unsigned long long inter;
+    unsigned long long visits[2];
     uint32_t status;
 };
 
@@ -79,15 +80,15 @@ struct tc_tree {
     uint32_t* perm = nullptr;
     Buf sort_temp, scan_temp, bounds_part;
     // node-sized
-    Buf level, first, count, next, nchild, cs, gidx, parent, list, nm, nx, wn;
+    Buf level, first, count, next, nchild, bfs, nk0, nk1, nv0, nv1, node_sort_temp, wn, diag_temp;
+    uint32_t* bfs_to_pre = nullptr;  // inside nv0 or nv1
     // small device block
     Buf small;
     Geom* geom = nullptr;
     uint32_t* level_hist = nullptr;
-    uint32_t* level_cursor = nullptr;
-    uint32_t* level_off_dev = nullptr;
     double* diag_out = nullptr;
     unsigned long long* inter_total = nullptr;
+    unsigned long long* visits = nullptr;      // [2]
     uint32_t* status = nullptr;
 
     HostMirror* host = nullptr;
@@ -95,6 +96,7 @@ struct tc_tree {
     tc_walk last_mode = TC_WALK_F32C;
     bool counted = false;
     bool diag_pending = false;
+    bool build_pending = false;
     Geom geom_host{};
 
     bool timing = false;
@@ -189,7 +191,7 @@ tc_status create_tree(tc_tree** out, hipStream_t s)
         t->freef = g_free ? g_free : default_free;
         t->actx = g_alloc ? g_actx : nullptr;
     }
-    size_t small = sizeof(Geom) + 4 * (3 * (kLevels + 2)) + 8 * 4 + 8 + 8 + 64;
+    size_t small = 1024;
     tc_status st = ensure(t, t->small, small, s);
     if (st != TC_OK) {
         delete t;
@@ -202,11 +204,9 @@ tc_status create_tree(tc_tree** out, hipStream_t s)
     p += 4 * sizeof(double);
     t->inter_total = (unsigned long long*)p;
     p += 8;
+    t->visits = (unsigned long long*)p;
+    p += 16;
     t->level_hist = (uint32_t*)p;
-    p += 4 * (kLevels + 2);
-    t->level_cursor = (uint32_t*)p;
-    p += 4 * (kLevels + 2);
-    t->level_off_dev = (uint32_t*)p;
     p += 4 * (kLevels + 2);
     t->status = (uint32_t*)p;
     if (hipHostMalloc((void**)&t->host, sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
@@ -235,7 +235,9 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     t->nn = 0;
     t->dtype = dt;
     t->diag_pending = false;
+    t->build_pending = false;
     t->counted = false;
+    for (int l = 0; l < kLevels + 2; ++l) t->host->level_hist[l] = 0;
     if (n == 0) {
         Geom g{};
         g.L = 1.0;
@@ -278,11 +280,11 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
 
     stage_begin(t, kStTree, s);
     launch_adjacent_levels(t->skeys, n, P<int8_t>(t->c), s);
-    launch_fill_u32(t->level_hist, kLevels, 0u, s);
+    launch_fill_u32(t->level_hist, kLevels + 2, 0u, s);
     launch_node_counts(P<int8_t>(t->c), n, P<uint32_t>(t->cnt), t->level_hist, s);
     launch_exclusive_scan_u32(P<uint32_t>(t->cnt), P<uint32_t>(t->pre), n, t->scan_temp.p, s);
     HIP_TRY(hipMemcpyAsync(&t->host->geom, t->geom, sizeof(Geom), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(t->host->level_hist, t->level_hist, 4 * kLevels, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(t->host->level_hist, t->level_hist, 4 * (kLevels + 2), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&t->host->total, P<uint32_t>(t->pre) + n, 4, hipMemcpyDeviceToHost, s));
     TC_TRY(check_launch("tree counts"));
     HIP_TRY(hipStreamSynchronize(s));
@@ -307,25 +309,20 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     TC_TRY(ensure(t, t->count, m4, s));
     TC_TRY(ensure(t, t->next, m4, s));
     TC_TRY(ensure(t, t->nchild, m4, s));
-    TC_TRY(ensure(t, t->cs, m4 + 8, s));
-    TC_TRY(ensure(t, t->gidx, m4, s));
-    TC_TRY(ensure(t, t->parent, m4, s));
-    TC_TRY(ensure(t, t->list, m4, s));
-    TC_TRY(ensure(t, t->nm, (size_t)nn * 8, s));
-    TC_TRY(ensure(t, t->nx, (size_t)nn * 24, s));
+    TC_TRY(ensure(t, t->bfs, m4, s));
+    TC_TRY(ensure(t, t->nk0, (size_t)nn * 8, s));
+    TC_TRY(ensure(t, t->nk1, (size_t)nn * 8, s));
+    TC_TRY(ensure(t, t->nv0, m4, s));
+    TC_TRY(ensure(t, t->nv1, m4, s));
+    TC_TRY(ensure(t, t->node_sort_temp, radix_temp_bytes(nn), s));
     TC_TRY(ensure(t, t->wn, (size_t)nn * sizeof(WalkNode), s));
-    TC_TRY(ensure(t, t->scan_temp, scan_temp_bytes(nn > n ? nn : n), s));
 
     launch_emit_nodes(t->skeys, P<int8_t>(t->c), P<uint32_t>(t->pre), n, P<uint8_t>(t->level), P<uint32_t>(t->first),
                       P<uint32_t>(t->count), P<uint32_t>(t->next), s);
     launch_count_children(P<uint8_t>(t->level), P<uint32_t>(t->count), P<uint32_t>(t->next), nn,
                           P<uint32_t>(t->nchild), s);
-    launch_exclusive_scan_u32(P<uint32_t>(t->nchild), P<uint32_t>(t->cs), nn, t->scan_temp.p, s);
-    launch_assign_groups(P<uint32_t>(t->next), P<uint32_t>(t->nchild), P<uint32_t>(t->cs), nn, P<uint32_t>(t->gidx),
-                         P<uint32_t>(t->parent), s);
-    HIP_TRY(hipMemcpyAsync(t->level_off_dev, t->host->level_off, 4 * (kLevels + 1), hipMemcpyHostToDevice, s));
-    launch_fill_u32(t->level_cursor, kLevels, 0u, s);
-    launch_level_lists(P<uint8_t>(t->level), nn, t->level_off_dev, t->level_cursor, P<uint32_t>(t->list), s);
+    launch_bfs_order(P<uint8_t>(t->level), nn, P<uint64_t>(t->nk0), P<uint32_t>(t->nv0), P<uint64_t>(t->nk1),
+                     P<uint32_t>(t->nv1), t->node_sort_temp.p, P<uint32_t>(t->bfs), &t->bfs_to_pre, s);
     stage_end(t, kStTree, s);
     TC_TRY(check_launch("tree"));
     t->state = 1;
@@ -336,10 +333,9 @@ tc_status moments_impl(tc_tree* t, hipStream_t s)
 {
     if (t->n > 0) {
         stage_begin(t, kStMoments, s);
-        launch_moments(P<uint32_t>(t->first), P<uint32_t>(t->count), P<uint32_t>(t->next), P<uint32_t>(t->nchild),
-                       P<uint32_t>(t->cs), P<uint32_t>(t->gidx), t->host->level_off, P<uint32_t>(t->list),
-                       t->skeys, P<double>(t->sx), P<double>(t->sy), P<double>(t->sz), P<double>(t->sm), t->geom,
-                       P<double>(t->nm), P<double>(t->nx), P<WalkNode>(t->wn), s);
+        launch_moments(t->host->level_off, t->bfs_to_pre, P<uint32_t>(t->bfs), P<uint32_t>(t->first),
+                       P<uint32_t>(t->count), P<uint32_t>(t->nchild), t->nn, t->skeys, P<double>(t->sx),
+                       P<double>(t->sy), P<double>(t->sz), P<double>(t->sm), t->geom, P<WalkNode>(t->wn), s);
         stage_end(t, kStMoments, s);
         TC_TRY(check_launch("moments"));
     }
@@ -362,6 +358,7 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     }
     const int64_t waves = walk_waves(n);
     TC_TRY(ensure(t, t->diag_part, (size_t)waves * 4 * sizeof(double), s));
+    TC_TRY(ensure(t, t->diag_temp, diag_temp_bytes(waves), s));
     if (t->counted) TC_TRY(ensure(t, t->sorted_counts, (size_t)n * 4, s));
 
     WalkArgs a{};
@@ -385,21 +382,25 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     a.counts = t->counted ? P<uint32_t>(t->sorted_counts) : nullptr;
     a.diag = P<double>(t->diag_part);
     a.status = t->status;
+    a.visits = t->visits;
 
     launch_fill_u32(t->status, 1, 0u, s);
+    if (t->counted) launch_fill_u32((uint32_t*)t->visits, 4, 0u, s);
     stage_begin(t, kStWalk, s);
     launch_walk(a, mode, t->counted, s);
     stage_end(t, kStWalk, s);
     TC_TRY(check_launch("walk"));
     stage_begin(t, kStDiag, s);
-    launch_diag_final(P<double>(t->diag_part), waves, t->diag_out, s);
+    launch_diag_final(P<double>(t->diag_part), waves, t->diag_temp.p, t->diag_out, s);
     if (t->counted) launch_sum_counts(P<uint32_t>(t->sorted_counts), n, t->inter_total, s);
     stage_end(t, kStDiag, s);
     TC_TRY(check_launch("diagnostics"));
     HIP_TRY(hipMemcpyAsync(t->host->diag, t->diag_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&t->host->status, t->status, 4, hipMemcpyDeviceToHost, s));
-    if (t->counted)
+    if (t->counted) {
         HIP_TRY(hipMemcpyAsync(&t->host->inter, t->inter_total, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(t->host->visits, t->visits, 16, hipMemcpyDeviceToHost, s));
+    }
     t->diag_pending = true;
     t->state |= 4u;
     return TC_OK;
@@ -489,10 +490,11 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
     memset(out, 0, sizeof *out);
     bool any_ev = false;
     for (int i = 0; i < kNumStages; ++i) any_ev |= t->ev_used[i];
-    if (t->diag_pending || any_ev) {
+    if (t->diag_pending || t->build_pending || any_ev) {
         TC_TRY(check_device(t));
         HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
         t->diag_pending = false;
+        t->build_pending = false;
     }
     out->n = t->n;
     out->n_nodes = t->nn;
@@ -504,11 +506,17 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
         if (t->n > 0 && (t->state & 1u) && t->host->level_hist[l]) maxl = l;
     out->max_level = maxl;
     out->state = t->state;
+    if (t->state & 1u) {
+        out->n_leaves = t->n > 0 ? (int64_t)t->host->level_hist[kLevels] : 0;
+        out->n_multi_leaves = t->n > 0 ? (int64_t)t->host->level_hist[kLevels + 1] : 0;
+    }
     out->last_mode = (uint32_t)t->last_mode;
     if (t->state & 4u) {
         for (int k = 0; k < 3; ++k) out->momentum[k] = t->host->diag[k];
         out->sum_m_abs_a = t->host->diag[3];
         out->interactions = t->counted ? t->host->inter : 0;
+        out->node_visits = t->counted ? t->host->visits[0] : 0;
+        out->lane_visits = t->counted ? t->host->visits[1] : 0;
     }
     for (int i = 0; i < 8; ++i) {
         out->stage_ms[i] = -1.0f;
@@ -553,8 +561,10 @@ tc_status tc_tree_export(const tc_tree* t, uint64_t* keys, uint32_t* perm, uint8
     TC_TRY(cp(level, t->level.p, nn));
     TC_TRY(cp(first, t->first.p, nn * 4));
     TC_TRY(cp(count, t->count.p, nn * 4));
-    TC_TRY(cp(com, t->nx.p, nn * 24));
-    TC_TRY(cp(mass, t->nm.p, nn * 8));
+    if (com || mass) {
+        launch_export_moments(P<WalkNode>(t->wn), P<uint32_t>(t->bfs), (int64_t)nn, com, mass, s);
+        TC_TRY(check_launch("export"));
+    }
     return TC_OK;
 }
 
@@ -574,8 +584,8 @@ void tc_tree_free(tc_tree* t)
     (void)hipDeviceSynchronize();
     Buf* bufs[] = {&t->keys0, &t->keys1, &t->vals0, &t->vals1, &t->sx, &t->sy, &t->sz, &t->sm, &t->c, &t->cnt,
                    &t->pre, &t->sorted_counts, &t->diag_part, &t->sort_temp, &t->scan_temp, &t->bounds_part,
-                   &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->cs, &t->gidx, &t->parent,
-                   &t->list, &t->nm, &t->nx, &t->wn, &t->small};
+                   &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->bfs, &t->nk0, &t->nk1,
+                   &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->small};
     for (Buf* b : bufs) release(t, *b);
     for (auto& e : t->ev)
         if (e) (void)hipEventDestroy(e);

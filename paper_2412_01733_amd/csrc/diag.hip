@@ -8,12 +8,16 @@ namespace {
 
 constexpr int kDiagThreads = 256;
 
-__global__ __launch_bounds__(kDiagThreads) void k_diag_final(const double* __restrict__ part, int64_t nw,
-                                                             double* __restrict__ out4)
+// Sum of rows [b*chunk, (b+1)*chunk) of a [nw, 4] array into out[b, 4], in a
+// fixed order (thread-strided partial sums, then a fixed tree).
+__global__ __launch_bounds__(kDiagThreads) void k_diag_reduce(const double* __restrict__ part, int64_t nw,
+                                                              int64_t chunk, double* __restrict__ out)
 {
     __shared__ double red[4][kDiagThreads];
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = threadIdx.x; i < nw; i += kDiagThreads)
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < nw ? b0 + chunk : nw;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += kDiagThreads)
         for (int k = 0; k < 4; ++k) v[k] += part[4 * i + k];
     for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
     __syncthreads();
@@ -23,7 +27,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_final(const double* __res
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) out4[k] = red[k][0];
+        for (int k = 0; k < 4; ++k) out[4 * blockIdx.x + k] = red[k][0];
 }
 
 __global__ __launch_bounds__(256) void k_sum_counts(const uint32_t* __restrict__ c, int64_t n,
@@ -53,9 +57,21 @@ __global__ __launch_bounds__(256) void k_scatter_counts(const uint32_t* __restri
 
 }  // namespace
 
-void launch_diag_final(const double* part, int64_t nwaves, double* out4, hipStream_t s)
+constexpr int64_t kDiagChunk = 2048;
+
+size_t diag_temp_bytes(int64_t nwaves)
 {
-    k_diag_final<<<1, kDiagThreads, 0, s>>>(part, nwaves, out4);
+    int64_t nb = (nwaves + kDiagChunk - 1) / kDiagChunk;
+    return (size_t)(nb + 1) * 4 * sizeof(double);
+}
+
+void launch_diag_final(const double* part, int64_t nwaves, void* temp, double* out4, hipStream_t s)
+{
+    int64_t nb = (nwaves + kDiagChunk - 1) / kDiagChunk;
+    if (nb < 1) nb = 1;
+    double* mid = (double*)temp;
+    k_diag_reduce<<<(unsigned)nb, kDiagThreads, 0, s>>>(part, nwaves, kDiagChunk, mid);
+    k_diag_reduce<<<1, kDiagThreads, 0, s>>>(mid, nb, nb, out4);
 }
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s)

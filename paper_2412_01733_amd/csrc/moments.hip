@@ -1,14 +1,16 @@
 // Upward pass: monopole moments of every node (TreeCode description of
 // section 2: a distant cell acts as its total mass at its centre of mass).
 //
-// One launch per level, deepest first, so a parent reads finished children.
+// One launch per level, deepest first, over that level's contiguous range of
+// the breadth-first node array, so a parent reads finished children, which
+// are consecutive records.
 // Everything is FP64 with no FMA contraction, summed in a fixed order
 // (particles in key order inside a leaf, children in octant order), so the
 // result does not depend on scheduling:
 //   leaf of one particle:  M = m_j, X = x_j exactly;
 //   otherwise:             M = sum M_c, X = (sum M_c X_c) / M,
 //                          X = the cell centre when M = 0.
-// The same launch writes the node's walk record in group order.
+// The same launch writes the node's whole walk record.
 #include "tc_internal.h"
 
 namespace tc {
@@ -36,29 +38,28 @@ __device__ inline void cell_centre(uint64_t key, int level, const Geom* g, doubl
 }
 
 __global__ __launch_bounds__(256) void k_moments_level(
-    int l, uint32_t cnt, const uint32_t* __restrict__ list, const uint32_t* __restrict__ first,
-    const uint32_t* __restrict__ count, const uint32_t* __restrict__ next,
-    const uint32_t* __restrict__ nchild, const uint32_t* __restrict__ cs,
-    const uint32_t* __restrict__ gidx, const uint64_t* __restrict__ skeys,
-    const double* __restrict__ sx, const double* __restrict__ sy, const double* __restrict__ sz,
-    const double* __restrict__ sm, const Geom* __restrict__ g, double* __restrict__ nm,
-    double* __restrict__ nx, WalkNode* __restrict__ wn)
+    int l, uint32_t b0, uint32_t b1, const uint32_t* __restrict__ bfs_to_pre, const uint32_t* __restrict__ bfs,
+    const uint32_t* __restrict__ first, const uint32_t* __restrict__ count, const uint32_t* __restrict__ nchild,
+    int64_t nn, const uint64_t* __restrict__ skeys, const double* __restrict__ sx, const double* __restrict__ sy,
+    const double* __restrict__ sz, const double* __restrict__ sm, const Geom* __restrict__ g,
+    WalkNode* __restrict__ wn)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += stride) {
-        const uint32_t p = list[t];
-        const uint32_t b = first[p], c = count[p], nc = nchild[p];
+    for (int64_t b = (int64_t)b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < (int64_t)b1; b += stride) {
+        const uint32_t p = bfs_to_pre[b];
+        const uint32_t f = first[p], c = count[p], nc = nchild[p];
         double M = 0.0, X[3];
         bool centre = false;
+        uint32_t child = 0;
         if (nc == 0) {
             if (c == 1) {
-                M = sm[b];
-                X[0] = sx[b];
-                X[1] = sy[b];
-                X[2] = sz[b];
+                M = sm[f];
+                X[0] = sx[f];
+                X[1] = sy[f];
+                X[2] = sz[f];
             } else {
                 double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-                for (uint32_t j = b; j < b + c; ++j) {
+                for (uint32_t j = f; j < f + c; ++j) {
                     const double mj = sm[j];
                     M += mj;
                     S0 += mj * sx[j];
@@ -73,15 +74,15 @@ __global__ __launch_bounds__(256) void k_moments_level(
                 }
             }
         } else {
+            child = bfs[p + 1];  // the first child follows its parent in pre-order
             double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-            uint32_t ch = p + 1;
             for (uint32_t k = 0; k < nc; ++k) {
-                const double mc = nm[ch];
+                const WalkNode& ch = wn[child + k];
+                const double mc = ch.m;
                 M += mc;
-                S0 += mc * nx[3 * (int64_t)ch + 0];
-                S1 += mc * nx[3 * (int64_t)ch + 1];
-                S2 += mc * nx[3 * (int64_t)ch + 2];
-                ch = next[ch];
+                S0 += mc * ch.x;
+                S1 += mc * ch.y;
+                S2 += mc * ch.z;
             }
             if (M == 0.0) centre = true;
             else {
@@ -90,40 +91,57 @@ __global__ __launch_bounds__(256) void k_moments_level(
                 X[2] = S2 / M;
             }
         }
-        if (centre) cell_centre(skeys[b], l, g, X);
-        nm[p] = M;
-        nx[3 * (int64_t)p + 0] = X[0];
-        nx[3 * (int64_t)p + 1] = X[1];
-        nx[3 * (int64_t)p + 2] = X[2];
+        if (centre) cell_centre(skeys[f], l, g, X);
         WalkNode r;
         r.x = X[0];
         r.y = X[1];
         r.z = X[2];
         r.m = M;
-        r.first = b;
+        r.first = f;
         r.count = c;
-        r.child = nc ? 1u + cs[p] : 0u;
+        r.child = child;
         r.meta = nc | ((uint32_t)l << 8) | (nc == 0 ? (1u << 16) : 0u);
-        wn[gidx[p]] = r;
+        wn[b] = r;
     }
+}
+
+__global__ __launch_bounds__(256) void k_export_moments(const WalkNode* __restrict__ wn,
+                                                        const uint32_t* __restrict__ bfs, int64_t nn,
+                                                        double* __restrict__ com, double* __restrict__ mass)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nn) return;
+    const WalkNode r = wn[bfs[p]];
+    if (com) {
+        com[3 * p + 0] = r.x;
+        com[3 * p + 1] = r.y;
+        com[3 * p + 2] = r.z;
+    }
+    if (mass) mass[p] = r.m;
 }
 
 }  // namespace
 
-void launch_moments(const uint32_t* first, const uint32_t* count, const uint32_t* next,
-                    const uint32_t* nchild, const uint32_t* cs, const uint32_t* gidx,
-                    const uint32_t* level_off_host, const uint32_t* list, const uint64_t* skeys,
-                    const double* sx, const double* sy, const double* sz, const double* sm,
-                    const Geom* geom, double* nm, double* nx, WalkNode* wn, hipStream_t s)
+void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
+                    const uint32_t* first, const uint32_t* count, const uint32_t* nchild, int64_t nn,
+                    const uint64_t* skeys, const double* sx, const double* sy, const double* sz,
+                    const double* sm, const Geom* geom, WalkNode* wn, hipStream_t s)
 {
     for (int l = kMaxLevel; l >= 0; --l) {
-        uint32_t cnt = level_off_host[l + 1] - level_off_host[l];
-        if (cnt == 0) continue;
-        unsigned blocks = (cnt + 255) / 256;
+        const uint32_t b0 = level_off_host[l], b1 = level_off_host[l + 1];
+        if (b1 <= b0) continue;
+        int64_t blocks = ((int64_t)(b1 - b0) + 255) / 256;
         if (blocks > 8192) blocks = 8192;
-        k_moments_level<<<blocks, 256, 0, s>>>(l, cnt, list + level_off_host[l], first, count, next, nchild,
-                                               cs, gidx, skeys, sx, sy, sz, sm, geom, nm, nx, wn);
+        k_moments_level<<<(unsigned)blocks, 256, 0, s>>>(l, b0, b1, bfs_to_pre, bfs, first, count, nchild, nn, skeys,
+                                                         sx, sy, sz, sm, geom, wn);
     }
+}
+
+void launch_export_moments(const WalkNode* wn, const uint32_t* bfs, int64_t nn, double* com, double* mass,
+                           hipStream_t s)
+{
+    if (nn == 0) return;
+    k_export_moments<<<(unsigned)((nn + 255) / 256), 256, 0, s>>>(wn, bfs, nn, com, mass);
 }
 
 }  // namespace tc

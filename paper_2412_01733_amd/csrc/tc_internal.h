@@ -25,9 +25,9 @@ struct Geom {
     uint32_t pad;
 };
 
-// One node as the walk reads it.  Nodes are stored in "group order": the
-// root at 0, and the children of every internal node contiguous (octant
-// order), groups laid out in the pre-order of their parents.
+// One node as the walk reads it.  Nodes are stored in breadth-first order:
+// sorted by (level, first), so the root is at 0, every level is contiguous
+// and the children of every internal node are consecutive in octant order.
 struct __align__(16) WalkNode {
     double x, y, z;   // centre of mass
     double m;         // total mass
@@ -70,23 +70,28 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32
 
 // build.hip
 void launch_adjacent_levels(const uint64_t* skeys, int64_t n, int8_t* c, hipStream_t s);
+// level_hist: [kLevels + 2] = nodes per level, leaves, multi-particle leaves
 void launch_node_counts(const int8_t* c, int64_t n, uint32_t* cnt, uint32_t* level_hist, hipStream_t s);
 void launch_emit_nodes(const uint64_t* skeys, const int8_t* c, const uint32_t* pre, int64_t n,
                        uint8_t* level, uint32_t* first, uint32_t* count, uint32_t* next,
                        hipStream_t s);
 void launch_count_children(const uint8_t* level, const uint32_t* count, const uint32_t* next,
                            int64_t nn, uint32_t* nchild, hipStream_t s);
-void launch_assign_groups(const uint32_t* next, const uint32_t* nchild, const uint32_t* cs,
-                          int64_t nn, uint32_t* gidx, uint32_t* parent, hipStream_t s);
-void launch_level_lists(const uint8_t* level, int64_t nn, const uint32_t* level_off,
-                        uint32_t* cursor, uint32_t* list, hipStream_t s);
+// Breadth-first order of the pre-order nodes (stable sort by level): writes
+// bfs[p] and points *bfs_to_pre at the inverse (inside v0 or v1).
+void launch_bfs_order(const uint8_t* level, int64_t nn, uint64_t* k0, uint32_t* v0, uint64_t* k1,
+                      uint32_t* v1, void* sort_temp, uint32_t* bfs, uint32_t** bfs_to_pre,
+                      hipStream_t s);
 
-// moments.hip (level_off_host: host copy of the per-level list offsets)
-void launch_moments(const uint32_t* first, const uint32_t* count, const uint32_t* next,
-                    const uint32_t* nchild, const uint32_t* cs, const uint32_t* gidx,
-                    const uint32_t* level_off_host, const uint32_t* list, const uint64_t* skeys,
-                    const double* sx, const double* sy, const double* sz, const double* sm,
-                    const Geom* geom, double* nm, double* nx, WalkNode* wn, hipStream_t s);
+// moments.hip: one launch per level over the breadth-first ranges
+// [level_off_host[l], level_off_host[l+1]), deepest level first.
+void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
+                    const uint32_t* first, const uint32_t* count, const uint32_t* nchild, int64_t nn,
+                    const uint64_t* skeys, const double* sx, const double* sy, const double* sz,
+                    const double* sm, const Geom* geom, WalkNode* wn, hipStream_t s);
+// Canonical export: com/mass of pre-order node p from wn[bfs[p]].
+void launch_export_moments(const WalkNode* wn, const uint32_t* bfs, int64_t nn, double* com, double* mass,
+                           hipStream_t s);
 
 // walk.hip
 struct WalkArgs {
@@ -106,12 +111,14 @@ struct WalkArgs {
     uint32_t* counts;       // sorted order (counting walk only)
     double* diag;           // [waves, 4] partials of sum m a, sum m |a|
     uint32_t* status;       // bit 0: stack overflow (never expected)
+    unsigned long long* visits;  // counting walk: [0] wave-level node evaluations, [1] sum of active lanes
 };
 int64_t walk_waves(int64_t n);
 void launch_walk(const WalkArgs& a, tc_walk mode, bool count, hipStream_t s);
 
 // diag.hip
-void launch_diag_final(const double* part, int64_t nwaves, double* out4, hipStream_t s);
+size_t diag_temp_bytes(int64_t nwaves);
+void launch_diag_final(const double* part, int64_t nwaves, void* temp, double* out4, hipStream_t s);
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 void launch_sum_counts(const uint32_t* counts, int64_t n, unsigned long long* out, hipStream_t s);
 void launch_scatter_counts(const uint32_t* sorted_counts, const uint32_t* perm, int64_t n,

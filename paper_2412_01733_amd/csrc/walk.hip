@@ -35,23 +35,26 @@ namespace {
 constexpr int kWalkWaves = 4;
 constexpr int kWalkThreads = 64 * kWalkWaves;
 // Pending groups never exceed 7 per level for levels 2..20 plus 8 at the
-// deepest level (<= 141); the bound below adds a margin.
-constexpr int kStack = 160;
+// deepest level (<= 141); the stack index is masked to its power-of-two size.
+constexpr int kStack = 256;
+// Group partial sums are folded into the compensated totals every few groups.
+constexpr int kFlushEvery = 4;
 
 struct StackEntry {
     uint32_t gs, nc, mlo, mhi;
 };
 
-struct __align__(16) Stg32 {
-    float x, y, z, m;
-    uint32_t first, count, child, meta;
-    float tau, p0, p1, p2;
+// What a child needs on the hot path, staged once per group in LDS.
+struct __align__(16) Hot32 {
+    float x, y, z, m;              // FP32 offsets from the wave anchor, mass
+    float tau;                     // opening threshold (s_l/theta)^2; -1 for a one-particle leaf
+    uint32_t first, count, child;
 };
 
-struct __align__(16) Stg64 {
+struct __align__(16) Hot64 {
     double x, y, z, m;
-    double tau, p0;
-    uint32_t first, count, child, meta;
+    double tau;
+    uint32_t first, count, child, pad;
 };
 
 __device__ inline void wave_sync()
@@ -62,6 +65,7 @@ __device__ inline void wave_sync()
 }
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // 1/sqrt(x) in FP64: hardware estimate refined by two Newton-Raphson steps
 // for f(y) = 1/y^2 - x, i.e. y <- y + y (1 - x y^2) / 2.
@@ -74,6 +78,9 @@ __device__ inline double rsqrt64(double x)
     y = fma(0.5 * y, r, y);
     return y;
 }
+
+__device__ inline float rsqrt_any(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsqrt_any(double x) { return rsqrt64(x); }
 
 __device__ inline void kahan_add(float& s, float& c, float v)
 {
@@ -95,9 +102,10 @@ template <bool F64, bool COUNT>
 __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
 {
     using R = typename std::conditional<F64, double, float>::type;
-    using Stg = typename std::conditional<F64, Stg64, Stg32>::type;
+    using Hot = typename std::conditional<F64, Hot64, Hot32>::type;
     __shared__ StackEntry stk[kWalkWaves][kStack];
-    __shared__ Stg stg[kWalkWaves][8];
+    __shared__ Hot stg[kWalkWaves][8];
+    __shared__ uint32_t stg_meta[kWalkWaves][8];
     __shared__ R tau_tab[kLevels];
 
     if (threadIdx.x < kLevels) {
@@ -115,6 +123,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     const bool valid = s < a.n;
     const int64_t sl = valid ? s : base;
     const uint32_t su = (uint32_t)s;
+    const uint32_t wave_end = (uint32_t)(base + 64 < a.n ? base + 64 : a.n);
 
     const double Ax = a.sx[base], Ay = a.sy[base], Az = a.sz[base];
     const double xs = a.sx[sl], ys = a.sy[sl], zs = a.sz[sl];
@@ -126,12 +135,15 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     }
     const R eps2 = (R)a.eps2;
 
-    // running totals: F32C keeps (sum, compensation) pairs
+    // running totals: F32C keeps (sum, compensation) pairs fed by plain partial sums
     R tx = 0, ty = 0, tz = 0, tp = 0;
     float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
+    R bx = 0, by = 0, bz = 0, bp = 0;
     uint32_t nint = 0;
+    uint64_t vis_nodes = 0, vis_lanes = 0;  // counting walk: wave-level node evaluations
 
     int sp = 0;
+    int since_flush = 0;
     const uint64_t vmask = __ballot(valid);
     {
         const uint32_t rmeta = uni(a.nodes[0].meta);
@@ -144,86 +156,83 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     wave_sync();
 
     while (sp > 0) {
-        --sp;
-        const StackEntry e = stk[w][sp];
+        sp = uni(sp - 1);
+        const StackEntry e = stk[w][sp & (kStack - 1)];
         const uint32_t gs = uni(e.gs);
-        uint32_t nc = uni(e.nc);
-        if (nc > 8) {  // impossible in an octree; keeps the staging in bounds
-            if (lane == 0) atomicOr(a.status, 2u);
-            nc = 8;
-        }
+        const uint32_t nc = uni(e.nc < 8u ? e.nc : 8u);
         const uint64_t mask = ((uint64_t)uni(e.mhi) << 32) | uni(e.mlo);
+        bool ovl = false;  // may the child contain one of this wave's targets?
         if (lane < nc) {
             const WalkNode nd = a.nodes[gs + lane];
-            Stg st;
+            ovl = nd.first < wave_end && nd.first + nd.count > (uint32_t)base;
+            Hot h;
             const bool single = meta_leaf(nd.meta) && nd.count == 1;
             if constexpr (F64) {
-                st.x = nd.x; st.y = nd.y; st.z = nd.z; st.m = nd.m;
+                h.x = nd.x; h.y = nd.y; h.z = nd.z; h.m = nd.m;
             } else {
-                st.x = (float)(nd.x - Ax); st.y = (float)(nd.y - Ay); st.z = (float)(nd.z - Az);
-                st.m = (float)nd.m;
+                h.x = (float)(nd.x - Ax); h.y = (float)(nd.y - Ay); h.z = (float)(nd.z - Az);
+                h.m = (float)nd.m;
             }
-            st.tau = single ? (R)-1 : tau_tab[meta_level(nd.meta)];
-            st.first = nd.first;
-            st.count = nd.count;
-            st.child = nd.child;
-            st.meta = nd.meta;
-            stg[w][lane] = st;
+            h.tau = single ? (R)-1 : tau_tab[meta_level(nd.meta)];
+            h.first = nd.first;
+            h.count = nd.count;
+            h.child = nd.child;
+            stg[w][lane] = h;
+            stg_meta[w][lane] = nd.meta;
         }
+        const uint64_t ovl_m = __ballot(ovl);
         wave_sync();
 
-        const bool act = (mask >> lane) & 1ull;
-        R bx = 0, by = 0, bz = 0, bp = 0;
-        for (uint32_t k = 0; k < nc; ++k) {
-            const R X = stg[w][k].x, Y = stg[w][k].y, Z = stg[w][k].z, M = stg[w][k].m;
-            const R tau = stg[w][k].tau;
-            const uint32_t f = uni(stg[w][k].first), cnt = uni(stg[w][k].count);
-            const R dx = X - px, dy = Y - py, dz = Z - pz;
+        if constexpr (COUNT) {
+            vis_nodes += nc;
+            vis_lanes += (uint64_t)nc * (uint64_t)__popcll(mask);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if ((uint32_t)k >= nc) break;
+            const Hot h = stg[w][k];  // one broadcast read of the whole record
+            const R dx = h.x - px, dy = h.y - py, dz = h.z - pz;
             const R d2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            const bool inside = (su - f) < cnt;
-            const bool accept = act && !inside && d2 > tau;
-            if (accept) {
-                R ri;
-                if constexpr (F64) ri = rsqrt64(d2 + eps2);
-                else ri = __builtin_amdgcn_rsqf(d2 + eps2);
-                const R mr = M * ri;
-                const R mr3 = mr * ri * ri;
+            // lane masks combined on the scalar unit: accepted = active, not containing, far enough
+            uint64_t in_m = 0;
+            if ((ovl_m >> k) & 1ull) in_m = __ballot((su - h.first) < h.count);
+            const uint64_t far_m = __ballot(d2 > h.tau);
+            const uint64_t am = mask & far_m & ~in_m;
+            if (__builtin_amdgcn_inverse_ballot_w64(am)) {
+                const R ri = rsqrt_any(d2 + eps2);
+                const R mr = h.m * ri;
+                const R mr3 = mr * (ri * ri);
                 bx = fma(mr3, dx, bx);
                 by = fma(mr3, dy, by);
                 bz = fma(mr3, dz, bz);
                 bp -= mr;
                 if constexpr (COUNT) ++nint;
             }
-            const bool open = act && !accept && !(tau < (R)0);
-            const uint64_t om = __ballot(open);
+            const uint64_t om = mask & ~am;
             if (om) {
-                const uint32_t meta = uni(stg[w][k].meta);
+                const uint32_t meta = uni(stg_meta[w][k]);
                 if (!meta_leaf(meta)) {
-                    const uint32_t child = uni(stg[w][k].child);
-                    if (sp < kStack) {
-                        if (lane == 0) stk[w][sp] = StackEntry{child, meta_nchild(meta), (uint32_t)om, (uint32_t)(om >> 32)};
-                        ++sp;
-                    } else if (lane == 0) {
-                        atomicOr(a.status, 1u);
-                    }
+                    const uint32_t child = uni(h.child);
+                    if (lane == 0) stk[w][sp & (kStack - 1)] = StackEntry{child, meta_nchild(meta), (uint32_t)om, (uint32_t)(om >> 32)};
+                    sp = uni(sp + 1);
                 } else {
-                    // particles of a multi-particle leaf, one by one (j != target)
+                    // an opened leaf: its particles one by one, the target itself excluded
+                    // (for a one-particle leaf only the lane holding that particle gets here)
+                    const uint32_t f = uni(h.first), cnt = uni(h.count);
+                    const bool lane_open = (om >> lane) & 1ull;
                     for (uint32_t j = f; j < f + cnt; ++j) {
                         const double xj = a.sx[j], yj = a.sy[j], zj = a.sz[j];
                         const R mj = (R)a.sm[j];
-                        if (open && j != su) {
+                        if (lane_open && j != su) {
                             R ex, ey, ez;
                             if constexpr (F64) {
                                 ex = xj - xs; ey = yj - ys; ez = zj - zs;
                             } else {
                                 ex = (float)(xj - Ax) - px; ey = (float)(yj - Ay) - py; ez = (float)(zj - Az) - pz;
                             }
-                            const R q = fma(ex, ex, fma(ey, ey, ez * ez)) + eps2;
-                            R ri;
-                            if constexpr (F64) ri = rsqrt64(q);
-                            else ri = __builtin_amdgcn_rsqf(q);
+                            const R ri = rsqrt_any(fma(ex, ex, fma(ey, ey, ez * ez)) + eps2);
                             const R mr = mj * ri;
-                            const R mr3 = mr * ri * ri;
+                            const R mr3 = mr * (ri * ri);
                             bx = fma(mr3, ex, bx);
                             by = fma(mr3, ey, by);
                             bz = fma(mr3, ez, bz);
@@ -235,15 +244,20 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
             }
         }
         wave_sync();
-        if constexpr (F64) {
-            tx += bx; ty += by; tz += bz; tp += bp;
-        } else {
-            kahan_add(tx, cx, bx);
-            kahan_add(ty, cy, by);
-            kahan_add(tz, cz, bz);
-            kahan_add(tp, cp, bp);
+        if (++since_flush == kFlushEvery || sp == 0) {
+            since_flush = 0;
+            if constexpr (F64) {
+                tx += bx; ty += by; tz += bz; tp += bp;
+            } else {
+                kahan_add(tx, cx, bx);
+                kahan_add(ty, cy, by);
+                kahan_add(tz, cz, bz);
+                kahan_add(tp, cp, bp);
+            }
+            bx = 0; by = 0; bz = 0; bp = 0;
         }
     }
+    if (sp < 0 || sp > kStack) atomicOr(a.status, 1u);
 
     R ox, oy, oz, op;
     if constexpr (F64) {
@@ -275,6 +289,10 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) a.diag[4 * wave_id + k] = dm[k];
+        if constexpr (COUNT) {
+            atomicAdd(&a.visits[0], (unsigned long long)vis_nodes);
+            atomicAdd(&a.visits[1], (unsigned long long)vis_lanes);
+        }
     }
 }
 

@@ -50,6 +50,8 @@ class Tree:
         self.n = 0
         self.device = None
         self._walk = None
+        self._timing = None
+        self._timing_applied = False
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -65,6 +67,9 @@ class Tree:
         with torch.cuda.device(pos.device):
             check(self._lib.tc_build(_ptr(pos), _ptr(mass), self.n, _DT[pos.dtype],
                                      _stream_ptr(pos.device), ctypes.byref(self._h)))
+            if self._timing is not None and not self._timing_applied:
+                check(self._lib.tc_tree_set_timing(self._h, 1 if self._timing else 0))
+                self._timing_applied = True
         self._keep = (pos, mass)
         return self
 
@@ -102,7 +107,10 @@ class Tree:
         return g_pos, g_mass
 
     def set_timing(self, on=True):
-        check(self._lib.tc_tree_set_timing(self._h, 1 if on else 0))
+        """Record per-stage HIP-event durations (applied at the next build if no handle yet)."""
+        self._timing = bool(on)
+        if self._h.value:
+            check(self._lib.tc_tree_set_timing(self._h, 1 if on else 0))
 
     def stats(self):
         s = _lib.TcStats()
@@ -110,7 +118,8 @@ class Tree:
             check(self._lib.tc_tree_stats(self._h, ctypes.byref(s), _stream_ptr(self.device)))
         return dict(n=s.n, n_nodes=s.n_nodes, n_leaves=s.n_leaves, n_multi_leaves=s.n_multi_leaves,
                     lo=list(s.lo), L=s.L, log2L=s.log2L, max_level=s.max_level, state=s.state,
-                    last_mode=s.last_mode, interactions=int(s.interactions), momentum=list(s.momentum),
+                    last_mode=s.last_mode, interactions=int(s.interactions), node_visits=int(s.node_visits),
+                    lane_visits=int(s.lane_visits), momentum=list(s.momentum),
                     sum_m_abs_a=s.sum_m_abs_a, stage_ms=list(s.stage_ms))
 
     def export(self, moments=True):

@@ -107,6 +107,12 @@ def test_tree_and_forces_match_oracle(name, make, theta, eps, walk):
         assert flips < 0.01, flips
     st = g["tree"].stats()
     assert st["interactions"] == int(g["counts"].sum())
+    nd = T.nodes()
+    assert st["n_nodes"] == T.nnodes
+    assert st["n_leaves"] == int((nd["nchild"] == 0).sum())
+    assert st["n_multi_leaves"] == int(((nd["nchild"] == 0) & (nd["count"] > 1)).sum())
+    # every target's interactions are evaluated by an active lane: counted work bounds
+    assert st["lane_visits"] >= st["interactions"] and 64 * st["node_visits"] >= st["lane_visits"]
 
 
 @pytest.mark.parametrize("walk", ["f32c", "f64"])
