@@ -100,7 +100,8 @@ tc_status tc_moments(tc_tree* tree, void* stream);
  *   particle order, FP32 for TC_WALK_F32C and FP64 for TC_WALK_F64.
  *   flags: TC_COUNT, TC_STORE_LISTS.
  * Errors: TC_ERR_INVALID (theta < 0 or not finite, eps < 0 or not finite, G
- * not finite, acc NULL with n > 0, bad mode or flags), TC_ERR_STATE (no
+ * not finite, acc NULL with n > 0, bad mode or flags, theta > 0 with
+ * (L/theta)^2 beyond the walk's float range), TC_ERR_STATE (no
  * tc_moments since the last tc_build), TC_ERR_NOMEM, TC_ERR_DEVICE. */
 tc_status tc_forces(tc_tree* tree, double theta, double eps, double G, tc_walk mode,
                     uint32_t flags, void* acc, void* pot, void* stream);

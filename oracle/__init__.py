@@ -62,6 +62,13 @@ def lib():
         L.or_tree_nodes.argtypes = [P] + [P] * 8
         L.or_tree_forces.argtypes = [P, D, D, D, P, I64, P, P, P, ctypes.c_int]
         L.or_direct.argtypes = [P, P, I64, D, D, P, I64, P, P, ctypes.c_int]
+        PP = ctypes.POINTER(ctypes.POINTER(ctypes.c_int64))
+        L.or_tree_lists.argtypes = [P, D, PP, PP, ctypes.c_int]
+        L.or_free.argtypes = [P]
+        L.or_frozen_forces.argtypes = [P, P, P, P, P, D, D, P, P]
+        L.or_frozen_adjoint.argtypes = [P, P, P, D, D, P, P, P, P]
+        L.or_leapfrog_step.argtypes = [P, P, P, P, P, I64, D, D, D, D, ctypes.c_int]
+        L.or_leapfrog_step.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -180,6 +187,57 @@ class Tree:
         lib().or_tree_forces(self._h, float(theta), float(eps), float(G), _ptr(tg), nt,
                              _ptr(acc), _ptr(pot), _ptr(nint), _threads(nthreads))
         return acc, pot, nint
+
+
+    # -- frozen interaction lists (for the adjoint) --------------------------
+    def lists(self, theta, nthreads=None):
+        """Every particle's interaction list (caller order) as CSR arrays
+        (offsets[n+1], codes): code >= 0 is a pre-order node, code < 0 the
+        particle at sorted position -(code + 1)."""
+        off = ctypes.POINTER(ctypes.c_int64)()
+        cod = ctypes.POINTER(ctypes.c_int64)()
+        lib().or_tree_lists(self._h, float(theta), ctypes.byref(off), ctypes.byref(cod), _threads(nthreads))
+        o = np.ctypeslib.as_array(off, shape=(self.n + 1,)).copy()
+        c = np.ctypeslib.as_array(cod, shape=(max(int(o[-1]), 1),))[:int(o[-1])].copy()
+        lib().or_free(ctypes.cast(off, ctypes.c_void_p))
+        lib().or_free(ctypes.cast(cod, ctypes.c_void_p))
+        return o, c
+
+    def frozen_forces(self, pos, mass, lists, eps, G=1.0):
+        """F(x, m; lists): forces with this tree's membership and the given lists frozen."""
+        x = _f64pos(pos)
+        m = np.ascontiguousarray(np.asarray(mass, dtype=np.float64).reshape(-1))
+        o, c = lists
+        acc = np.zeros((self.n, 3))
+        pot = np.zeros(self.n)
+        lib().or_frozen_forces(self._h, _ptr(x), _ptr(m), _ptr(o), _ptr(c), float(eps), float(G),
+                               _ptr(acc), _ptr(pot))
+        return acc, pot
+
+    def frozen_adjoint(self, lists, eps, g_acc, g_pot=None, G=1.0):
+        """(dL/dx [n,3], dL/dm [n]) of L(F(x, m; lists)) at this tree's (x, m)."""
+        o, c = lists
+        ga = np.ascontiguousarray(np.asarray(g_acc, dtype=np.float64).reshape(-1, 3))
+        gp = None if g_pot is None else np.ascontiguousarray(np.asarray(g_pot, dtype=np.float64))
+        gx = np.zeros((self.n, 3))
+        gm = np.zeros(self.n)
+        lib().or_frozen_adjoint(self._h, _ptr(o), _ptr(c), float(eps), float(G), _ptr(ga), _ptr(gp),
+                                _ptr(gx), _ptr(gm))
+        return gx, gm
+
+
+def leapfrog_step(pos, vel, mass, acc, tau, theta, eps, G=1.0, nthreads=None):
+    """One kick-drift-kick step, Eqs.(2)-(5) with a rebuild for Eq.(4).
+    Returns new (pos, vel, acc, pot) as FP64 arrays."""
+    x = _f64pos(pos).copy()
+    v = _f64pos(vel).copy()
+    a = _f64pos(acc).copy()
+    m = np.ascontiguousarray(np.asarray(mass, dtype=np.float64).reshape(-1))
+    pot = np.zeros(x.shape[0])
+    if lib().or_leapfrog_step(_ptr(x), _ptr(v), _ptr(m), _ptr(a), _ptr(pot), x.shape[0], float(tau),
+                              float(theta), float(eps), float(G), _threads(nthreads)) != 0:
+        raise ValueError("non-finite position after the drift")
+    return x, v, a, pot
 
 
 def direct(pos, mass, eps, G=1.0, targets=None, nthreads=None):

@@ -521,3 +521,265 @@ void or_direct(const double* pos, const double* m, int64_t n, double eps, double
     J.targets = targets; J.acc = acc; J.pot = pot;
     run_parallel(direct_task, &J, nt, nthreads);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Frozen interaction lists, the frozen-list evaluation and its adjoint      */
+/* ------------------------------------------------------------------------ */
+/*
+ * With the tree's membership (which particles each node holds) and every
+ * target's interaction set held fixed, the forces become a smooth function
+ * F(x, m; lists): node moments are recomputed from (x, m) by the same
+ * recursive definition, and each target sums Eq.(1) terms over its recorded
+ * sources.  A source code >= 0 is a pre-order node (its monopole), a code
+ * < 0 is the particle with sorted position -(code + 1) (a direct term).
+ */
+
+typedef struct {
+    const or_tree* T;
+    double theta;
+    int64_t* cnt;      /* per target: number of sources */
+    int64_t** codes;   /* per target: the sources in visit order */
+    const int64_t* targets;
+} lists_job;
+
+static void push_code(int64_t** buf, int64_t* n, int64_t* cap, int64_t code)
+{
+    if (*n == *cap) {
+        *cap = *cap ? 2 * *cap : 64;
+        *buf = (int64_t*)realloc(*buf, sizeof(int64_t) * (size_t)*cap);
+    }
+    (*buf)[(*n)++] = code;
+}
+
+static void lists_rec(const or_tree* T, double theta, int64_t id, int64_t si, const double x[3],
+                      int64_t** buf, int64_t* n, int64_t* cap)
+{
+    int64_t b = T->first[id], e = b + T->count[id];
+    if (si >= b && si < e) {
+        if (is_leaf(T, id)) {
+            for (int64_t j = b; j < e; ++j)
+                if (j != si) push_code(buf, n, cap, -(j + 1));
+        } else {
+            for (int c = 0; c < T->nchild[id]; ++c) lists_rec(T, theta, T->child[8 * id + c], si, x, buf, n, cap);
+        }
+        return;
+    }
+    const double* X = &T->com[3 * id];
+    double d[3] = {X[0] - x[0], X[1] - x[1], X[2] - x[2]};
+    double dist = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double side = ldexp(T->L, -T->level[id]);
+    if (theta > 0.0 && side < theta * dist) {
+        push_code(buf, n, cap, id);
+    } else if (is_leaf(T, id)) {
+        for (int64_t j = b; j < e; ++j) push_code(buf, n, cap, -(j + 1));
+    } else {
+        for (int c = 0; c < T->nchild[id]; ++c) lists_rec(T, theta, T->child[8 * id + c], si, x, buf, n, cap);
+    }
+}
+
+static void lists_task(void* p, int64_t t)
+{
+    lists_job* J = (lists_job*)p;
+    const or_tree* T = J->T;
+    int64_t i = J->targets ? J->targets[t] : t;
+    int64_t si = T->spos[i];
+    int64_t n = 0, cap = 0;
+    int64_t* buf = NULL;
+    if (T->nn > 0) lists_rec(T, J->theta, 0, si, &T->sx[3 * si], &buf, &n, &cap);
+    J->cnt[t] = n;
+    J->codes[t] = buf;
+}
+
+/* The interaction list of every particle (caller order) in CSR form:
+ * *offsets [n+1] and *codes [offsets[n]], both malloc'd (free with
+ * or_free). */
+void or_tree_lists(const or_tree* T, double theta, int64_t** offsets, int64_t** codes, int nthreads)
+{
+    int64_t n = T->n;
+    lists_job J;
+    J.T = T; J.theta = theta; J.targets = NULL;
+    J.cnt = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    J.codes = (int64_t**)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t*));
+    run_parallel(lists_task, &J, n, nthreads);
+    int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    off[0] = 0;
+    for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + J.cnt[i];
+    int64_t* all = (int64_t*)malloc(sizeof(int64_t) * (size_t)(off[n] > 0 ? off[n] : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        if (J.cnt[i]) memcpy(all + off[i], J.codes[i], sizeof(int64_t) * (size_t)J.cnt[i]);
+        free(J.codes[i]);
+    }
+    free(J.cnt);
+    free(J.codes);
+    *offsets = off;
+    *codes = all;
+}
+
+void or_free(void* p) { free(p); }
+
+/* Node moments of the frozen tree for new particle data (caller order
+ * pos[n,3], m[n]): same recursion as the build (children in octant order). */
+static void frozen_moments(const or_tree* T, const double* pos, const double* m, double* sx, double* sm,
+                           double* com, double* mass)
+{
+    for (int64_t s = 0; s < T->n; ++s) {
+        int64_t i = T->perm[s];
+        for (int k = 0; k < 3; ++k) sx[3 * s + k] = pos[3 * i + k];
+        sm[s] = m[i];
+    }
+    for (int64_t id = T->nn - 1; id >= 0; --id) {
+        double M = 0.0, S[3] = {0.0, 0.0, 0.0};
+        if (is_leaf(T, id)) {
+            int64_t b = T->first[id], e = b + T->count[id];
+            if (e - b == 1) {
+                mass[id] = sm[b];
+                for (int k = 0; k < 3; ++k) com[3 * id + k] = sx[3 * b + k];
+                continue;
+            }
+            for (int64_t j = b; j < e; ++j) {
+                M += sm[j];
+                for (int k = 0; k < 3; ++k) S[k] += sm[j] * sx[3 * j + k];
+            }
+        } else {
+            for (int c = 0; c < T->nchild[id]; ++c) {
+                int64_t ch = T->child[8 * id + c];
+                M += mass[ch];
+                for (int k = 0; k < 3; ++k) S[k] += mass[ch] * com[3 * ch + k];
+            }
+        }
+        mass[id] = M;
+        if (M == 0.0) {
+            for (int k = 0; k < 3; ++k) com[3 * id + k] = T->com[3 * id + k];  /* cell centre, fixed */
+        } else {
+            for (int k = 0; k < 3; ++k) com[3 * id + k] = S[k] / M;
+        }
+    }
+}
+
+/* F(x, m; lists): accelerations and potentials (caller order) with the tree
+ * membership and the lists frozen. */
+void or_frozen_forces(const or_tree* T, const double* pos, const double* m, const int64_t* offsets,
+                      const int64_t* codes, double eps, double G, double* acc, double* pot)
+{
+    int64_t n = T->n, nn = T->nn;
+    double* sx = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double* sm = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* com = (double*)malloc(sizeof(double) * 3 * (size_t)(nn > 0 ? nn : 1));
+    double* mass = (double*)malloc(sizeof(double) * (size_t)(nn > 0 ? nn : 1));
+    frozen_moments(T, pos, m, sx, sm, com, mass);
+    double eps2 = eps * eps;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t si = T->spos[i];
+        acc_t r;
+        memset(&r, 0, sizeof r);
+        for (int64_t q = offsets[i]; q < offsets[i + 1]; ++q) {
+            int64_t c = codes[q];
+            if (c >= 0) term(&r, &sx[3 * si], &com[3 * c], mass[c], eps2, G);
+            else term(&r, &sx[3 * si], &sx[3 * (-c - 1)], sm[-c - 1], eps2, G);
+        }
+        for (int k = 0; k < 3; ++k) acc[3 * i + k] = r.a[k];
+        if (pot) pot[i] = r.phi;
+    }
+    free(sx); free(sm); free(com); free(mass);
+}
+
+/* Adjoint of F(x, m; lists).  Given g_acc = dL/da [n,3] and g_pot = dL/dphi
+ * [n] (may be NULL), writes g_pos = dL/dx [n,3] and g_mass = dL/dm [n]
+ * (caller order).  For one term with Delta = y - x_i, q = |Delta|^2 + eps^2,
+ * T = q^-3/2 I - 3 q^-5/2 Delta Delta^T:
+ *   da/dy = G mu T, da/dx_i = -G mu T, da/dmu = G Delta q^-3/2,
+ *   dphi/dy = G mu Delta q^-3/2, dphi/dx_i = -G mu Delta q^-3/2, dphi/dmu = -G q^-1/2.
+ * A node source carries dL/dX_n and dL/dM_n down to its particles through
+ * M_n = sum m_j and X_n = sum m_j x_j / M_n: with u_n = (dL/dX_n) / M_n and
+ * c_n = dL/dM_n - u_n . X_n, every particle j gets dL/dm_j += c_n + u_n . x_j
+ * and dL/dx_j += m_j u_n, summed over the nodes that hold it (top-down
+ * prefix sums).  A node of zero mass sits at its fixed cell centre: it has
+ * u_n = 0. */
+void or_frozen_adjoint(const or_tree* T, const int64_t* offsets, const int64_t* codes, double eps, double G,
+                       const double* g_acc, const double* g_pot, double* g_pos, double* g_mass)
+{
+    int64_t n = T->n, nn = T->nn;
+    double eps2 = eps * eps;
+    double* gX = (double*)calloc((size_t)(3 * (nn > 0 ? nn : 1)), sizeof(double));
+    double* gM = (double*)calloc((size_t)(nn > 0 ? nn : 1), sizeof(double));
+    double* gx = (double*)calloc((size_t)(3 * (n > 0 ? n : 1)), sizeof(double));  /* sorted order */
+    double* gm = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t si = T->spos[i];
+        const double* x = &T->sx[3 * si];
+        const double* g = &g_acc[3 * i];
+        double h = g_pot ? g_pot[i] : 0.0;
+        for (int64_t q = offsets[i]; q < offsets[i + 1]; ++q) {
+            int64_t c = codes[q];
+            const double* y;
+            double mu;
+            if (c >= 0) { y = &T->com[3 * c]; mu = T->mass[c]; }
+            else { y = &T->sx[3 * (-c - 1)]; mu = T->sm[-c - 1]; }
+            double d[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+            double qq = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+            double inv = 1.0 / sqrt(qq);
+            double inv3 = inv * inv * inv;
+            double inv5 = inv3 * inv * inv;
+            double dg = d[0] * g[0] + d[1] * g[1] + d[2] * g[2];
+            double gy[3], gmu;
+            for (int k = 0; k < 3; ++k) gy[k] = G * mu * (inv3 * g[k] - 3.0 * inv5 * d[k] * dg + inv3 * d[k] * h);
+            gmu = G * (dg * inv3 - h * inv);
+            for (int k = 0; k < 3; ++k) gx[3 * si + k] -= gy[k];
+            if (c >= 0) {
+                for (int k = 0; k < 3; ++k) gX[3 * c + k] += gy[k];
+                gM[c] += gmu;
+            } else {
+                int64_t j = -c - 1;
+                for (int k = 0; k < 3; ++k) gx[3 * j + k] += gy[k];
+                gm[j] += gmu;
+            }
+        }
+    }
+    /* top-down: prefix sums of u and c along every root-to-leaf path */
+    double* U = (double*)calloc((size_t)(3 * (nn > 0 ? nn : 1)), sizeof(double));
+    double* C = (double*)calloc((size_t)(nn > 0 ? nn : 1), sizeof(double));
+    for (int64_t id = 0; id < nn; ++id) {           /* parents precede children */
+        double u[3] = {0.0, 0.0, 0.0}, cc;
+        double M = T->mass[id];
+        if (M != 0.0)
+            for (int k = 0; k < 3; ++k) u[k] = gX[3 * id + k] / M;
+        cc = gM[id] - (u[0] * T->com[3 * id] + u[1] * T->com[3 * id + 1] + u[2] * T->com[3 * id + 2]);
+        int64_t p = T->parent[id];
+        for (int k = 0; k < 3; ++k) U[3 * id + k] = (p >= 0 ? U[3 * p + k] : 0.0) + u[k];
+        C[id] = (p >= 0 ? C[p] : 0.0) + cc;
+        if (is_leaf(T, id)) {
+            for (int64_t j = T->first[id]; j < T->first[id] + T->count[id]; ++j) {
+                const double* xj = &T->sx[3 * j];
+                gm[j] += C[id] + U[3 * id] * xj[0] + U[3 * id + 1] * xj[1] + U[3 * id + 2] * xj[2];
+                for (int k = 0; k < 3; ++k) gx[3 * j + k] += T->sm[j] * U[3 * id + k];
+            }
+        }
+    }
+    for (int64_t s = 0; s < n; ++s) {
+        int64_t i = T->perm[s];
+        for (int k = 0; k < 3; ++k) g_pos[3 * i + k] = gx[3 * s + k];
+        g_mass[i] = gm[s];
+    }
+    free(gX); free(gM); free(gx); free(gm); free(U); free(C);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kick-drift-kick leapfrog, Eqs.(2)-(5)                                      */
+/* ------------------------------------------------------------------------ */
+
+/* One step on caller-order arrays (updated in place): v += tau/2 a;
+ * x += tau v; a = Barnes-Hut forces of a tree rebuilt at the new x;
+ * v += tau/2 a.  pot (may be NULL) receives the new potentials.  Returns 0,
+ * or -1 if the rebuilt tree is rejected (non-finite position). */
+int or_leapfrog_step(double* pos, double* vel, const double* m, double* acc, double* pot, int64_t n,
+                     double tau, double theta, double eps, double G, int nthreads)
+{
+    for (int64_t i = 0; i < 3 * n; ++i) vel[i] += 0.5 * tau * acc[i];
+    for (int64_t i = 0; i < 3 * n; ++i) pos[i] += tau * vel[i];
+    or_tree* T = or_tree_new(pos, m, n);
+    if (!T) return -1;
+    or_tree_forces(T, theta, eps, G, NULL, n, acc, pot, NULL, nthreads);
+    or_tree_free(T);
+    for (int64_t i = 0; i < 3 * n; ++i) vel[i] += 0.5 * tau * acc[i];
+    return 0;
+}

@@ -371,11 +371,13 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     a.n = n;
     a.eps2 = eps * eps;
     a.G = G;
-    for (int l = 0; l < kLevels; ++l) {
-        double side = std::ldexp(t->geom_host.L, -l);
-        double tv = theta > 0.0 ? (side / theta) * (side / theta) : INFINITY;
-        a.tau64[l] = tv;
-        a.tau32[l] = (float)tv;
+    {
+        const double side = t->geom_host.L;
+        const double tv = theta > 0.0 ? (side / theta) * (side / theta) : INFINITY;
+        a.tau0_64 = tv;
+        a.tau0_32 = (float)tv;
+        if (theta > 0.0 && (!std::isfinite(tv) || (mode == TC_WALK_F32C && !std::isfinite(a.tau0_32))))
+            return fail(TC_ERR_INVALID, "tc_forces: (L/theta)^2 = (%g/%g)^2 overflows the walk precision", side, theta);
     }
     a.acc = acc;
     a.pot = pot;

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_moments_level(
         r.first = f;
         r.count = c;
         r.child = child;
-        r.meta = nc | ((uint32_t)l << 8) | (nc == 0 ? (1u << 16) : 0u);
+        r.meta = nc | ((uint32_t)l << 8) | (nc == 0 ? (1u << 16) : 0u) | (nc == 0 && c == 1 ? (1u << 17) : 0u);
         wn[b] = r;
     }
 }

@@ -34,13 +34,14 @@ struct __align__(16) WalkNode {
     uint32_t first;   // sorted index of the first particle
     uint32_t count;   // particles in the node
     uint32_t child;   // group index of the first child (internal nodes)
-    uint32_t meta;    // bits 0-3 nchild, bits 8-12 level, bit 16 leaf
+    uint32_t meta;    // bits 0-3 nchild, bits 8-12 level, bit 16 leaf, bit 17 one-particle leaf
 };
 static_assert(sizeof(WalkNode) == 48, "WalkNode layout");
 
 __host__ __device__ inline uint32_t meta_nchild(uint32_t m) { return m & 0xFu; }
 __host__ __device__ inline uint32_t meta_level(uint32_t m) { return (m >> 8) & 0x1Fu; }
 __host__ __device__ inline bool meta_leaf(uint32_t m) { return (m >> 16) & 1u; }
+__host__ __device__ inline bool meta_single(uint32_t m) { return (m >> 17) & 1u; }
 
 // ---------------------------------------------------------------------------
 // launch wrappers (each defined next to its kernels)
@@ -104,8 +105,8 @@ struct WalkArgs {
     int64_t n;
     double eps2;
     double G;
-    double tau64[kLevels];  // (s_l / theta)^2, +inf for theta == 0
-    float tau32[kLevels];
+    double tau0_64;         // (L / theta)^2, +inf for theta == 0; level l uses tau0 4^-l
+    float tau0_32;          // the same rounded to FP32 (scaling by 4^-l stays exact)
     void* acc;              // caller order, FP32 (F32C) or FP64 (F64)
     void* pot;              // may be NULL
     uint32_t* counts;       // sorted order (counting walk only)

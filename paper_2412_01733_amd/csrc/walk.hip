@@ -106,13 +106,9 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     __shared__ StackEntry stk[kWalkWaves][kStack];
     __shared__ Hot stg[kWalkWaves][8];
     __shared__ uint32_t stg_meta[kWalkWaves][8];
-    __shared__ R tau_tab[kLevels];
-
-    if (threadIdx.x < kLevels) {
-        if constexpr (F64) tau_tab[threadIdx.x] = a.tau64[threadIdx.x];
-        else tau_tab[threadIdx.x] = a.tau32[threadIdx.x];
-    }
-    __syncthreads();
+    R tau0;
+    if constexpr (F64) tau0 = a.tau0_64;
+    else tau0 = a.tau0_32;
 
     const int w = threadIdx.x >> 6;
     const uint32_t lane = threadIdx.x & 63;
@@ -162,18 +158,20 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
         const uint32_t nc = uni(e.nc < 8u ? e.nc : 8u);
         const uint64_t mask = ((uint64_t)uni(e.mhi) << 32) | uni(e.mlo);
         bool ovl = false;  // may the child contain one of this wave's targets?
+        const WalkNode* grp = a.nodes + gs;  // uniform base of the group
         if (lane < nc) {
-            const WalkNode nd = a.nodes[gs + lane];
+            const WalkNode nd = grp[lane];
             ovl = nd.first < wave_end && nd.first + nd.count > (uint32_t)base;
             Hot h;
-            const bool single = meta_leaf(nd.meta) && nd.count == 1;
+            const bool single = meta_single(nd.meta);
             if constexpr (F64) {
                 h.x = nd.x; h.y = nd.y; h.z = nd.z; h.m = nd.m;
             } else {
                 h.x = (float)(nd.x - Ax); h.y = (float)(nd.y - Ay); h.z = (float)(nd.z - Az);
                 h.m = (float)nd.m;
             }
-            h.tau = single ? (R)-1 : tau_tab[meta_level(nd.meta)];
+            // (s_l/theta)^2 = tau0 4^-l: an exact power-of-two scaling
+            h.tau = single ? (R)-1 : (R)ldexp(tau0, -2 * (int)meta_level(nd.meta));
             h.first = nd.first;
             h.count = nd.count;
             h.child = nd.child;
