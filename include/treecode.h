@@ -121,7 +121,10 @@ tc_status tc_forces_backward(tc_tree* tree, const void* g_acc, const void* g_pot
  * place; acc holds a^n on entry and a^{n+1} on exit; pot (may be NULL)
  * receives phi^{n+1}.  pos/vel/mass are of `dtype`; acc/pot are of the walk
  * precision (FP32 for F32C, FP64 for F64).  *tree as for tc_build.
- * Blocks once (inside the rebuild).  Errors: as tc_build and tc_forces. */
+ * Blocks once (inside the rebuild).  Errors: as tc_build and tc_forces;
+ * arguments are checked before anything is written, but an error raised by
+ * the rebuild (TC_ERR_INPUT, TC_ERR_NOMEM, ...) leaves pos and vel at the
+ * drifted state of Eqs.(2)-(3). */
 tc_status tc_leapfrog_step(tc_tree** tree, void* pos, void* vel, const void* mass,
                            void* acc, void* pot, int64_t n, tc_dtype dtype, double tau,
                            double theta, double eps, double G, tc_walk mode, void* stream);
@@ -143,6 +146,10 @@ typedef struct {
     uint64_t lane_visits;    /* TC_COUNT: the same weighted by the lanes active at each evaluation */
     double momentum[3];      /* sum_i m_i a_i of the last tc_forces (FP64) */
     double sum_m_abs_a;      /* sum_i m_i |a_i| (FP64) */
+    double kinetic;          /* after the last tc_leapfrog_step (FP64): sum m v^2 / 2 */
+    double potential;        /*   sum m phi / 2 (0 if pot was NULL) */
+    double lin_momentum[3];  /*   sum m v */
+    double ang_momentum[3];  /*   sum m x cross v */
     float stage_ms[8];       /* last timed durations: 0 keys, 1 sort, 2 tree, 3 moments,
                                 4 walk, 5 diagnostics, 6 backward walk, 7 backward down-pass
                                 (-1 if not recorded) */

@@ -41,6 +41,10 @@ class TcStats(ctypes.Structure):
         ("lane_visits", ctypes.c_uint64),
         ("momentum", ctypes.c_double * 3),
         ("sum_m_abs_a", ctypes.c_double),
+        ("kinetic", ctypes.c_double),
+        ("potential", ctypes.c_double),
+        ("lin_momentum", ctypes.c_double * 3),
+        ("ang_momentum", ctypes.c_double * 3),
         ("stage_ms", ctypes.c_float * 8),
     ]
 

@@ -21,7 +21,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtreecode.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["keys.hip", "scan.hip", "sort.hip", "build.hip", "moments.hip", "walk.hip", "diag.hip", "capi.hip"]
+SOURCES = ["keys.hip", "scan.hip", "sort.hip", "build.hip", "moments.hip", "walk.hip", "adjoint.hip", "diag.hip",
+           "integrate.hip", "capi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=off",

@@ -59,6 +59,7 @@ struct HostMirror {
     double diag[4];
     unsigned long long inter;
     unsigned long long visits[2];
+    double step[10];
     uint32_t status;
 };
 
@@ -80,13 +81,16 @@ struct tc_tree {
     uint32_t* perm = nullptr;
     Buf sort_temp, scan_temp, bounds_part;
     // node-sized
-    Buf level, first, count, next, nchild, bfs, nk0, nk1, nv0, nv1, node_sort_temp, wn, diag_temp;
+    Buf level, first, count, next, nchild, bfs, nk0, nk1, nv0, nv1, node_sort_temp, wn, diag_temp, parent;
+    // adjoint and leapfrog
+    Buf node_grad, uc, part_grad, target_grad, step_temp;
     uint32_t* bfs_to_pre = nullptr;  // inside nv0 or nv1
     // small device block
     Buf small;
     Geom* geom = nullptr;
     uint32_t* level_hist = nullptr;
     double* diag_out = nullptr;
+    double* step_out = nullptr;  // [10]
     unsigned long long* inter_total = nullptr;
     unsigned long long* visits = nullptr;      // [2]
     uint32_t* status = nullptr;
@@ -97,6 +101,9 @@ struct tc_tree {
     bool counted = false;
     bool diag_pending = false;
     bool build_pending = false;
+    bool step_pending = false;
+    bool step_valid = false;
+    double f_theta = 0.0, f_eps = 0.0, f_G = 1.0;  // parameters of the last tc_forces
     Geom geom_host{};
 
     bool timing = false;
@@ -202,6 +209,8 @@ tc_status create_tree(tc_tree** out, hipStream_t s)
     p += (sizeof(Geom) + 15) & ~(size_t)15;
     t->diag_out = (double*)p;
     p += 4 * sizeof(double);
+    t->step_out = (double*)p;
+    p += 10 * sizeof(double);
     t->inter_total = (unsigned long long*)p;
     p += 8;
     t->visits = (unsigned long long*)p;
@@ -316,6 +325,7 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     TC_TRY(ensure(t, t->nv1, m4, s));
     TC_TRY(ensure(t, t->node_sort_temp, radix_temp_bytes(nn), s));
     TC_TRY(ensure(t, t->wn, (size_t)nn * sizeof(WalkNode), s));
+    TC_TRY(ensure(t, t->parent, m4, s));
 
     launch_emit_nodes(t->skeys, P<int8_t>(t->c), P<uint32_t>(t->pre), n, P<uint8_t>(t->level), P<uint32_t>(t->first),
                       P<uint32_t>(t->count), P<uint32_t>(t->next), s);
@@ -335,11 +345,35 @@ tc_status moments_impl(tc_tree* t, hipStream_t s)
         stage_begin(t, kStMoments, s);
         launch_moments(t->host->level_off, t->bfs_to_pre, P<uint32_t>(t->bfs), P<uint32_t>(t->first),
                        P<uint32_t>(t->count), P<uint32_t>(t->nchild), t->nn, t->skeys, P<double>(t->sx),
-                       P<double>(t->sy), P<double>(t->sz), P<double>(t->sm), t->geom, P<WalkNode>(t->wn), s);
+                       P<double>(t->sy), P<double>(t->sz), P<double>(t->sm), t->geom, P<WalkNode>(t->wn),
+                       P<uint32_t>(t->parent), s);
         stage_end(t, kStMoments, s);
         TC_TRY(check_launch("moments"));
     }
     t->state |= 2u;
+    return TC_OK;
+}
+
+// The walk's common arguments: tree arrays, softening, G and the opening
+// threshold tau_l = (L 2^-l / theta)^2 = tau_0 4^-l.
+tc_status walk_args(tc_tree* t, double theta, double eps, double G, tc_walk mode, WalkArgs& a)
+{
+    a.nodes = P<WalkNode>(t->wn);
+    a.sx = P<double>(t->sx);
+    a.sy = P<double>(t->sy);
+    a.sz = P<double>(t->sz);
+    a.sm = P<double>(t->sm);
+    a.perm = t->perm;
+    a.n = t->n;
+    a.eps2 = eps * eps;
+    a.G = G;
+    const double side = t->geom_host.L;
+    const double tv = theta > 0.0 ? (side / theta) * (side / theta) : INFINITY;
+    a.tau0_64 = tv;
+    a.tau0_32 = (float)tv;
+    if (theta > 0.0 && (!std::isfinite(tv) || (mode == TC_WALK_F32C && !std::isfinite(a.tau0_32))))
+        return fail(TC_ERR_INVALID, "tc_forces: (L/theta)^2 = (%g/%g)^2 overflows the walk precision", side, theta);
+    a.status = t->status;
     return TC_OK;
 }
 
@@ -349,6 +383,9 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     const int64_t n = t->n;
     t->last_mode = mode;
     t->counted = (flags & TC_COUNT) != 0;
+    t->f_theta = theta;
+    t->f_eps = eps;
+    t->f_G = G;
     if (n == 0) {
         t->state |= 4u;
         t->host->diag[0] = t->host->diag[1] = t->host->diag[2] = t->host->diag[3] = 0.0;
@@ -362,23 +399,7 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     if (t->counted) TC_TRY(ensure(t, t->sorted_counts, (size_t)n * 4, s));
 
     WalkArgs a{};
-    a.nodes = P<WalkNode>(t->wn);
-    a.sx = P<double>(t->sx);
-    a.sy = P<double>(t->sy);
-    a.sz = P<double>(t->sz);
-    a.sm = P<double>(t->sm);
-    a.perm = t->perm;
-    a.n = n;
-    a.eps2 = eps * eps;
-    a.G = G;
-    {
-        const double side = t->geom_host.L;
-        const double tv = theta > 0.0 ? (side / theta) * (side / theta) : INFINITY;
-        a.tau0_64 = tv;
-        a.tau0_32 = (float)tv;
-        if (theta > 0.0 && (!std::isfinite(tv) || (mode == TC_WALK_F32C && !std::isfinite(a.tau0_32))))
-            return fail(TC_ERR_INVALID, "tc_forces: (L/theta)^2 = (%g/%g)^2 overflows the walk precision", side, theta);
-    }
+    TC_TRY(walk_args(t, theta, eps, G, mode, a));
     a.acc = acc;
     a.pot = pot;
     a.counts = t->counted ? P<uint32_t>(t->sorted_counts) : nullptr;
@@ -409,6 +430,37 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
 }
 
 bool is_finite(double v) { return std::isfinite(v); }
+
+tc_status backward_impl(tc_tree* t, const void* g_acc, const void* g_pot, void* g_pos, void* g_mass, hipStream_t s)
+{
+    const int64_t n = t->n, nn = t->nn;
+    if (n == 0) return TC_OK;
+    TC_TRY(ensure(t, t->node_grad, (size_t)nn * 4 * sizeof(double), s));
+    TC_TRY(ensure(t, t->uc, (size_t)nn * 4 * sizeof(double), s));
+    TC_TRY(ensure(t, t->part_grad, (size_t)n * 4 * sizeof(double), s));
+    TC_TRY(ensure(t, t->target_grad, (size_t)n * 3 * sizeof(double), s));
+    WalkArgs a{};
+    TC_TRY(walk_args(t, t->f_theta, t->f_eps, t->f_G, t->last_mode, a));
+    a.g_acc = g_acc;
+    a.g_pot = g_pot;
+    a.node_grad = P<double>(t->node_grad);
+    a.part_grad = P<double>(t->part_grad);
+    a.target_grad = P<double>(t->target_grad);
+    stage_begin(t, kStBwdWalk, s);
+    launch_fill_f64_zero(a.node_grad, nn * 4, s);
+    launch_fill_f64_zero(a.part_grad, n * 4, s);
+    launch_fill_u32(t->status, 1, 0u, s);
+    launch_walk_adjoint(a, t->last_mode, s);
+    stage_end(t, kStBwdWalk, s);
+    TC_TRY(check_launch("adjoint walk"));
+    stage_begin(t, kStBwdDown, s);
+    launch_adjoint_down(t->host->level_off, P<WalkNode>(t->wn), P<uint32_t>(t->parent), a.node_grad, P<double>(t->uc),
+                        a.sx, a.sy, a.sz, a.sm, t->perm, a.target_grad, a.part_grad, g_pos, g_mass,
+                        t->last_mode == TC_WALK_F64, s);
+    stage_end(t, kStBwdDown, s);
+    TC_TRY(check_launch("adjoint down-pass"));
+    return TC_OK;
+}
 
 }  // namespace
 
@@ -469,20 +521,55 @@ tc_status tc_forces(tc_tree* t, double theta, double eps, double G, tc_walk mode
 tc_status tc_forces_backward(tc_tree* t, const void* g_acc, const void* g_pot, void* g_pos, void* g_mass,
                              void* stream)
 {
-    (void)g_acc; (void)g_pot; (void)g_pos; (void)g_mass; (void)stream;
     g_err.clear();
     if (!t) return fail(TC_ERR_INVALID, "tc_forces_backward: tree is NULL");
-    return fail(TC_ERR_STATE, "tc_forces_backward: not available in this build");
+    if (!(t->state & 4u)) return fail(TC_ERR_STATE, "tc_forces_backward: no tc_forces since the last tc_build");
+    if (t->n > 0 && !g_acc) return fail(TC_ERR_INVALID, "tc_forces_backward: g_acc must be non-NULL");
+    TC_TRY(check_device(t));
+    return backward_impl(t, g_acc, g_pot, g_pos, g_mass, (hipStream_t)stream);
 }
 
 tc_status tc_leapfrog_step(tc_tree** tree, void* pos, void* vel, const void* mass, void* acc, void* pot,
                            int64_t n, tc_dtype dtype, double tau, double theta, double eps, double G, tc_walk mode,
                            void* stream)
 {
-    (void)tree; (void)pos; (void)vel; (void)mass; (void)acc; (void)pot; (void)n; (void)dtype; (void)tau;
-    (void)theta; (void)eps; (void)G; (void)mode; (void)stream;
     g_err.clear();
-    return fail(TC_ERR_STATE, "tc_leapfrog_step: not available in this build");
+    if (!tree) return fail(TC_ERR_INVALID, "tc_leapfrog_step: tree is NULL");
+    if (n < 0 || n >= (int64_t)1 << 31) return fail(TC_ERR_INVALID, "tc_leapfrog_step: n out of range");
+    if (dtype != TC_F32 && dtype != TC_F64) return fail(TC_ERR_INVALID, "tc_leapfrog_step: bad dtype");
+    if (n > 0 && (!pos || !vel || !mass || !acc))
+        return fail(TC_ERR_INVALID, "tc_leapfrog_step: pos, vel, mass and acc must be non-NULL");
+    if (!is_finite(tau)) return fail(TC_ERR_INVALID, "tc_leapfrog_step: tau must be finite");
+    if (!is_finite(theta) || theta < 0.0) return fail(TC_ERR_INVALID, "tc_leapfrog_step: theta must be finite and >= 0");
+    if (!is_finite(eps) || eps < 0.0) return fail(TC_ERR_INVALID, "tc_leapfrog_step: eps must be finite and >= 0");
+    if (!is_finite(G)) return fail(TC_ERR_INVALID, "tc_leapfrog_step: G must be finite");
+    if (mode != TC_WALK_F32C && mode != TC_WALK_F64) return fail(TC_ERR_INVALID, "tc_leapfrog_step: bad walk mode");
+    hipStream_t s = (hipStream_t)stream;
+    const bool acc64 = mode == TC_WALK_F64;
+    if (!*tree) {
+        TC_TRY(create_tree(tree, s));
+    } else {
+        TC_TRY(check_device(*tree));
+    }
+    tc_tree* t = *tree;
+    launch_kick_drift(pos, vel, acc, n, dtype, acc64, tau, s);            // Eqs.(2), (3)
+    TC_TRY(check_launch("kick-drift"));
+    TC_TRY(build_impl(t, pos, mass, n, dtype, s));                       // Eq.(4): rebuild ...
+    TC_TRY(moments_impl(t, s));
+    TC_TRY(forces_impl(t, theta, eps, G, mode, 0u, acc, pot, s));        // ... and evaluate
+    launch_kick(vel, acc, n, dtype, acc64, tau, s);                      // Eq.(5)
+    TC_TRY(check_launch("kick"));
+    if (n > 0) {
+        TC_TRY(ensure(t, t->step_temp, step_diag_temp_bytes(), s));
+        launch_step_diag(pos, vel, mass, pot, n, dtype, acc64, t->step_temp.p, t->step_out, s);
+        TC_TRY(check_launch("step diagnostics"));
+        HIP_TRY(hipMemcpyAsync(t->host->step, t->step_out, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
+        t->step_pending = true;
+    } else {
+        for (int k = 0; k < 10; ++k) t->host->step[k] = 0.0;
+    }
+    t->step_valid = true;
+    return TC_OK;
 }
 
 tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
@@ -492,11 +579,12 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
     memset(out, 0, sizeof *out);
     bool any_ev = false;
     for (int i = 0; i < kNumStages; ++i) any_ev |= t->ev_used[i];
-    if (t->diag_pending || t->build_pending || any_ev) {
+    if (t->diag_pending || t->build_pending || t->step_pending || any_ev) {
         TC_TRY(check_device(t));
         HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
         t->diag_pending = false;
         t->build_pending = false;
+        t->step_pending = false;
     }
     out->n = t->n;
     out->n_nodes = t->nn;
@@ -519,6 +607,14 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
         out->interactions = t->counted ? t->host->inter : 0;
         out->node_visits = t->counted ? t->host->visits[0] : 0;
         out->lane_visits = t->counted ? t->host->visits[1] : 0;
+    }
+    if (t->step_valid) {
+        out->kinetic = t->host->step[0];
+        out->potential = t->host->step[1];
+        for (int k = 0; k < 3; ++k) {
+            out->lin_momentum[k] = t->host->step[2 + k];
+            out->ang_momentum[k] = t->host->step[5 + k];
+        }
     }
     for (int i = 0; i < 8; ++i) {
         out->stage_ms[i] = -1.0f;
@@ -587,7 +683,8 @@ void tc_tree_free(tc_tree* t)
     Buf* bufs[] = {&t->keys0, &t->keys1, &t->vals0, &t->vals1, &t->sx, &t->sy, &t->sz, &t->sm, &t->c, &t->cnt,
                    &t->pre, &t->sorted_counts, &t->diag_part, &t->sort_temp, &t->scan_temp, &t->bounds_part,
                    &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->bfs, &t->nk0, &t->nk1,
-                   &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->small};
+                   &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->parent, &t->node_grad,
+                   &t->uc, &t->part_grad, &t->target_grad, &t->step_temp, &t->small};
     for (Buf* b : bufs) release(t, *b);
     for (auto& e : t->ev)
         if (e) (void)hipEventDestroy(e);

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_moments_level(
     const uint32_t* __restrict__ first, const uint32_t* __restrict__ count, const uint32_t* __restrict__ nchild,
     int64_t nn, const uint64_t* __restrict__ skeys, const double* __restrict__ sx, const double* __restrict__ sy,
     const double* __restrict__ sz, const double* __restrict__ sm, const Geom* __restrict__ g,
-    WalkNode* __restrict__ wn)
+    WalkNode* __restrict__ wn, uint32_t* __restrict__ parent)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = (int64_t)b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < (int64_t)b1; b += stride) {
@@ -77,6 +77,7 @@ __global__ __launch_bounds__(256) void k_moments_level(
             child = bfs[p + 1];  // the first child follows its parent in pre-order
             double S0 = 0.0, S1 = 0.0, S2 = 0.0;
             for (uint32_t k = 0; k < nc; ++k) {
+                parent[child + k] = (uint32_t)b;
                 const WalkNode& ch = wn[child + k];
                 const double mc = ch.m;
                 M += mc;
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(256) void k_export_moments(const WalkNode* __restri
 void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
                     const uint32_t* first, const uint32_t* count, const uint32_t* nchild, int64_t nn,
                     const uint64_t* skeys, const double* sx, const double* sy, const double* sz,
-                    const double* sm, const Geom* geom, WalkNode* wn, hipStream_t s)
+                    const double* sm, const Geom* geom, WalkNode* wn, uint32_t* parent, hipStream_t s)
 {
     for (int l = kMaxLevel; l >= 0; --l) {
         const uint32_t b0 = level_off_host[l], b1 = level_off_host[l + 1];
@@ -133,7 +134,7 @@ void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, 
         int64_t blocks = ((int64_t)(b1 - b0) + 255) / 256;
         if (blocks > 8192) blocks = 8192;
         k_moments_level<<<(unsigned)blocks, 256, 0, s>>>(l, b0, b1, bfs_to_pre, bfs, first, count, nchild, nn, skeys,
-                                                         sx, sy, sz, sm, geom, wn);
+                                                         sx, sy, sz, sm, geom, wn, parent);
     }
 }
 

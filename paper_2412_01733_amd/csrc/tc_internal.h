@@ -89,7 +89,7 @@ void launch_bfs_order(const uint8_t* level, int64_t nn, uint64_t* k0, uint32_t* 
 void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
                     const uint32_t* first, const uint32_t* count, const uint32_t* nchild, int64_t nn,
                     const uint64_t* skeys, const double* sx, const double* sy, const double* sz,
-                    const double* sm, const Geom* geom, WalkNode* wn, hipStream_t s);
+                    const double* sm, const Geom* geom, WalkNode* wn, uint32_t* parent, hipStream_t s);
 // Canonical export: com/mass of pre-order node p from wn[bfs[p]].
 void launch_export_moments(const WalkNode* wn, const uint32_t* bfs, int64_t nn, double* com, double* mass,
                            hipStream_t s);
@@ -113,9 +113,32 @@ struct WalkArgs {
     double* diag;           // [waves, 4] partials of sum m a, sum m |a|
     uint32_t* status;       // bit 0: stack overflow (never expected)
     unsigned long long* visits;  // counting walk: [0] wave-level node evaluations, [1] sum of active lanes
+    // adjoint walk only
+    const void* g_acc;      // dL/da [n,3], caller order, walk precision
+    const void* g_pot;      // dL/dphi [n] or NULL
+    double* node_grad;      // [nodes, 4] breadth-first: dL/dX (3), dL/dM, accumulated
+    double* part_grad;      // [n, 4] sorted order: dL/dx_j (3), dL/dm_j from opened multi-particle leaves
+    double* target_grad;    // [n, 3] sorted order: dL/dx_i from the target side
 };
 int64_t walk_waves(int64_t n);
 void launch_walk(const WalkArgs& a, tc_walk mode, bool count, hipStream_t s);
+void launch_walk_adjoint(const WalkArgs& a, tc_walk mode, hipStream_t s);
+
+// adjoint.hip: top-down pass from node gradients to particle gradients.
+void launch_adjoint_down(const uint32_t* level_off_host, const WalkNode* wn, const uint32_t* parent,
+                         const double* node_grad, double* uc, const double* sx, const double* sy,
+                         const double* sz, const double* sm, const uint32_t* perm, const double* target_grad,
+                         const double* part_grad, void* g_pos, void* g_mass, bool out_f64, hipStream_t s);
+void launch_fill_f64_zero(double* p, int64_t n, hipStream_t s);
+
+// integrate.hip: leapfrog pieces and FP64 step diagnostics
+void launch_kick_drift(void* pos, void* vel, const void* acc, int64_t n, tc_dtype dt, bool acc64, double tau,
+                       hipStream_t s);
+void launch_kick(void* vel, const void* acc, int64_t n, tc_dtype dt, bool acc64, double tau, hipStream_t s);
+size_t step_diag_temp_bytes();
+// out10: kinetic, potential energy, momentum (3), angular momentum (3), total mass, 0
+void launch_step_diag(const void* pos, const void* vel, const void* mass, const void* pot, int64_t n, tc_dtype dt,
+                      bool pot64, void* temp, double* out10, hipStream_t s);
 
 // diag.hip
 size_t diag_temp_bytes(int64_t nwaves);

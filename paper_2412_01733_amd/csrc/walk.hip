@@ -25,6 +25,10 @@
 // FP64 reciprocal square root refined by two Newton-Raphson steps, plain FP64
 // sums.  Both walks also reduce sum_i m_i a_i and sum_i m_i |a_i| in FP64,
 // one partial per wave, for the momentum diagnostic.
+//
+// The adjoint walk (tc_forces_backward) is the same kernel with ADJ = true:
+// it re-walks the tree with the same decisions and differentiates every
+// term, the tree membership and the interaction sets held fixed.
 #include <type_traits>
 
 #include "tc_internal.h"
@@ -98,7 +102,54 @@ __device__ inline R wave_sum(R v)
     return v;
 }
 
-template <bool F64, bool COUNT>
+// Adjoint of one term (mass mu at offset (dx,dy,dz) from the target,
+// q = d^2 + eps^2) for dL/da = (gx,gy,gz), dL/dphi = h.  With
+// T = q^-3/2 I - 3 q^-5/2 Delta Delta^T the source receives
+//   dL/dy  = G mu (T g + q^-3/2 Delta h)   (the target receives the negative),
+//   dL/dmu = G (Delta.g q^-3/2 - h q^-1/2).
+template <typename R>
+__device__ inline void adj_term(R dx, R dy, R dz, R q, R mu, R G, R gx, R gy, R gz, R h, R& sx, R& sy, R& sz,
+                                R& sm)
+{
+    const R ri = rsqrt_any(q);
+    const R ri2 = ri * ri;
+    const R ri3 = ri2 * ri;
+    const R dg = fma(dx, gx, fma(dy, gy, dz * gz));
+    const R c1 = G * mu * ri3;
+    const R c2 = c1 * fma((R)-3 * ri2, dg, h);
+    sx = fma(c1, gx, c2 * dx);
+    sy = fma(c1, gy, c2 * dy);
+    sz = fma(c1, gz, c2 * dz);
+    sm = G * fma(dg, ri3, -h * ri);
+}
+
+// Sum over the wave of four values; the result is uniform.
+template <typename R>
+__device__ inline void wave_sum4(R& a0, R& a1, R& a2, R& a3)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, 64);
+        a1 += __shfl_xor(a1, o, 64);
+        a2 += __shfl_xor(a2, o, 64);
+        a3 += __shfl_xor(a3, o, 64);
+    }
+}
+
+__device__ inline void add4(double* dst, double v0, double v1, double v2, double v3)
+{
+    unsafeAtomicAdd(dst + 0, v0);
+    unsafeAtomicAdd(dst + 1, v1);
+    unsafeAtomicAdd(dst + 2, v2);
+    unsafeAtomicAdd(dst + 3, v3);
+}
+
+// ADJ = false: accelerations and potentials.  ADJ = true: the adjoint walk
+// with identical traversal and decisions (same code, same arithmetic), which
+// writes the target-side gradient per particle and accumulates the
+// source-side gradients per node (and per particle for opened
+// multi-particle leaves) with FP64 atomics after a wave reduction.
+template <bool F64, bool COUNT, bool ADJ>
 __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
 {
     using R = typename std::conditional<F64, double, float>::type;
@@ -130,6 +181,18 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
         px = (float)(xs - Ax); py = (float)(ys - Ay); pz = (float)(zs - Az);
     }
     const R eps2 = (R)a.eps2;
+    const R Gc = (R)a.G;
+    R gxl = 0, gyl = 0, gzl = 0, hl = 0;  // adjoint: dL/da and dL/dphi of this lane's target
+    if constexpr (ADJ) {
+        if (valid) {
+            const uint32_t i = a.perm[s];
+            const R* ga = (const R*)a.g_acc;
+            gxl = ga[3 * (int64_t)i + 0];
+            gyl = ga[3 * (int64_t)i + 1];
+            gzl = ga[3 * (int64_t)i + 2];
+            if (a.g_pot) hl = ((const R*)a.g_pot)[i];
+        }
+    }
 
     // running totals: F32C keeps (sum, compensation) pairs fed by plain partial sums
     R tx = 0, ty = 0, tz = 0, tp = 0;
@@ -196,15 +259,29 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
             if ((ovl_m >> k) & 1ull) in_m = __ballot((su - h.first) < h.count);
             const uint64_t far_m = __ballot(d2 > h.tau);
             const uint64_t am = mask & far_m & ~in_m;
-            if (__builtin_amdgcn_inverse_ballot_w64(am)) {
-                const R ri = rsqrt_any(d2 + eps2);
-                const R mr = h.m * ri;
-                const R mr3 = mr * (ri * ri);
-                bx = fma(mr3, dx, bx);
-                by = fma(mr3, dy, by);
-                bz = fma(mr3, dz, bz);
-                bp -= mr;
-                if constexpr (COUNT) ++nint;
+            if constexpr (!ADJ) {
+                if (__builtin_amdgcn_inverse_ballot_w64(am)) {
+                    const R ri = rsqrt_any(d2 + eps2);
+                    const R mr = h.m * ri;
+                    const R mr3 = mr * (ri * ri);
+                    bx = fma(mr3, dx, bx);
+                    by = fma(mr3, dy, by);
+                    bz = fma(mr3, dz, bz);
+                    bp -= mr;
+                    if constexpr (COUNT) ++nint;
+                }
+            } else {
+                if (am) {
+                    R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
+                    if (__builtin_amdgcn_inverse_ballot_w64(am)) {
+                        adj_term(dx, dy, dz, d2 + eps2, h.m, Gc, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
+                        bx -= sx0;
+                        by -= sy0;
+                        bz -= sz0;
+                    }
+                    wave_sum4(sx0, sy0, sz0, sm0);
+                    if (lane == 0) add4(a.node_grad + 4 * (int64_t)(gs + k), sx0, sy0, sz0, sm0);
+                }
             }
             const uint64_t om = mask & ~am;
             if (om) {
@@ -221,6 +298,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                     for (uint32_t j = f; j < f + cnt; ++j) {
                         const double xj = a.sx[j], yj = a.sy[j], zj = a.sz[j];
                         const R mj = (R)a.sm[j];
+                        R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
                         if (lane_open && j != su) {
                             R ex, ey, ez;
                             if constexpr (F64) {
@@ -228,14 +306,26 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                             } else {
                                 ex = (float)(xj - Ax) - px; ey = (float)(yj - Ay) - py; ez = (float)(zj - Az) - pz;
                             }
-                            const R ri = rsqrt_any(fma(ex, ex, fma(ey, ey, ez * ez)) + eps2);
-                            const R mr = mj * ri;
-                            const R mr3 = mr * (ri * ri);
-                            bx = fma(mr3, ex, bx);
-                            by = fma(mr3, ey, by);
-                            bz = fma(mr3, ez, bz);
-                            bp -= mr;
+                            const R q = fma(ex, ex, fma(ey, ey, ez * ez)) + eps2;
+                            if constexpr (!ADJ) {
+                                const R ri = rsqrt_any(q);
+                                const R mr = mj * ri;
+                                const R mr3 = mr * (ri * ri);
+                                bx = fma(mr3, ex, bx);
+                                by = fma(mr3, ey, by);
+                                bz = fma(mr3, ez, bz);
+                                bp -= mr;
+                            } else {
+                                adj_term(ex, ey, ez, q, mj, Gc, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
+                                bx -= sx0;
+                                by -= sy0;
+                                bz -= sz0;
+                            }
                             if constexpr (COUNT) ++nint;
+                        }
+                        if constexpr (ADJ) {
+                            wave_sum4(sx0, sy0, sz0, sm0);
+                            if (lane == 0) add4(a.part_grad + 4 * (int64_t)j, sx0, sy0, sz0, sm0);
                         }
                     }
                 }
@@ -257,14 +347,24 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     }
     if (sp < 0 || sp > kStack) atomicOr(a.status, 1u);
 
+    if constexpr (ADJ) {
+        if (valid) {
+            double* tg = a.target_grad + 3 * s;
+            if constexpr (F64) {
+                tg[0] = tx; tg[1] = ty; tg[2] = tz;
+            } else {
+                tg[0] = (double)(tx - cx); tg[1] = (double)(ty - cy); tg[2] = (double)(tz - cz);
+            }
+        }
+        return;
+    }
     R ox, oy, oz, op;
     if constexpr (F64) {
         ox = tx; oy = ty; oz = tz; op = tp;
     } else {
         ox = tx - cx; oy = ty - cy; oz = tz - cz; op = tp - cp;
     }
-    const R G = (R)a.G;
-    ox *= G; oy *= G; oz *= G; op *= G;
+    ox *= Gc; oy *= Gc; oz *= Gc; op *= Gc;
 
     double dm[4] = {0.0, 0.0, 0.0, 0.0};
     if (valid) {
@@ -304,12 +404,21 @@ void launch_walk(const WalkArgs& a, tc_walk mode, bool count, hipStream_t s)
     const int64_t waves = walk_waves(a.n);
     const unsigned blocks = (unsigned)((waves + kWalkWaves - 1) / kWalkWaves);
     if (mode == TC_WALK_F64) {
-        if (count) k_walk<true, true><<<blocks, kWalkThreads, 0, s>>>(a);
-        else k_walk<true, false><<<blocks, kWalkThreads, 0, s>>>(a);
+        if (count) k_walk<true, true, false><<<blocks, kWalkThreads, 0, s>>>(a);
+        else k_walk<true, false, false><<<blocks, kWalkThreads, 0, s>>>(a);
     } else {
-        if (count) k_walk<false, true><<<blocks, kWalkThreads, 0, s>>>(a);
-        else k_walk<false, false><<<blocks, kWalkThreads, 0, s>>>(a);
+        if (count) k_walk<false, true, false><<<blocks, kWalkThreads, 0, s>>>(a);
+        else k_walk<false, false, false><<<blocks, kWalkThreads, 0, s>>>(a);
     }
+}
+
+void launch_walk_adjoint(const WalkArgs& a, tc_walk mode, hipStream_t s)
+{
+    if (a.n == 0) return;
+    const int64_t waves = walk_waves(a.n);
+    const unsigned blocks = (unsigned)((waves + kWalkWaves - 1) / kWalkWaves);
+    if (mode == TC_WALK_F64) k_walk<true, false, true><<<blocks, kWalkThreads, 0, s>>>(a);
+    else k_walk<false, false, true><<<blocks, kWalkThreads, 0, s>>>(a);
 }
 
 }  // namespace tc

@@ -4,7 +4,7 @@ torch supplies device memory and the stream; every step of the computation
 runs in the library's HIP kernels.  Functions here mirror the C ABI names:
 
   Tree.build / Tree.moments / Tree.forces   -> tc_build / tc_moments / tc_forces
-  Tree.backward                             -> tc_forces_backward
+  Tree.backward, TreeForces (autograd)      -> tc_forces_backward
   leapfrog_step                             -> tc_leapfrog_step
   forces(pos, mass, theta, eps, ...)        -> build + moments + forces
 """
@@ -120,7 +120,9 @@ class Tree:
                     lo=list(s.lo), L=s.L, log2L=s.log2L, max_level=s.max_level, state=s.state,
                     last_mode=s.last_mode, interactions=int(s.interactions), node_visits=int(s.node_visits),
                     lane_visits=int(s.lane_visits), momentum=list(s.momentum),
-                    sum_m_abs_a=s.sum_m_abs_a, stage_ms=list(s.stage_ms))
+                    sum_m_abs_a=s.sum_m_abs_a, kinetic=s.kinetic, potential=s.potential,
+                    lin_momentum=list(s.lin_momentum), ang_momentum=list(s.ang_momentum),
+                    stage_ms=list(s.stage_ms))
 
     def export(self, moments=True):
         st = self.stats()
@@ -147,6 +149,64 @@ class Tree:
         with torch.cuda.device(self.device):
             check(self._lib.tc_interaction_counts(self._h, _ptr(c), _stream_ptr(self.device)))
         return c
+
+
+class TreeForces(torch.autograd.Function):
+    """(acc, pot) = TreeForces.apply(pos, mass, theta, eps, G, walk).
+
+    Forward: tc_build + tc_moments + tc_forces.  Backward: tc_forces_backward,
+    the adjoint of the same walk with the tree membership and every
+    interaction set held fixed (the opening decisions are piecewise constant
+    in x, so this is the derivative wherever no decision sits on its
+    threshold).  Gradients come back in the dtype of pos.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, mass, theta, eps, G=1.0, walk="f32c"):
+        tree = Tree()
+        tree.build(pos.detach(), mass.detach()).moments()
+        acc, pot = tree.forces(theta, eps, G, walk=walk)
+        ctx.tree = tree
+        ctx.in_dtype = pos.dtype
+        return acc, pot
+
+    @staticmethod
+    def backward(ctx, g_acc, g_pot):
+        tree = ctx.tree
+        if g_acc is None:
+            dt = torch.float32 if tree._walk == "f32c" else torch.float64
+            g_acc = torch.zeros((tree.n, 3), dtype=dt, device=tree.device)
+        gpos, gmass = tree.backward(g_acc, g_pot, need_pos=ctx.needs_input_grad[0],
+                                    need_mass=ctx.needs_input_grad[1])
+        gpos = gpos.to(ctx.in_dtype) if gpos is not None else None
+        gmass = gmass.to(ctx.in_dtype) if gmass is not None else None
+        return gpos, gmass, None, None, None, None
+
+
+def leapfrog_step(pos, vel, mass, acc, tau, theta, eps, G=1.0, walk="f32c", pot=None, tree=None):
+    """One kick-drift-kick step (Eqs.(2)-(5)) in place through tc_leapfrog_step.
+
+    pos, vel, mass: [n,3], [n,3], [n] of one float dtype; acc (and pot) are of
+    the walk's precision and hold a^n on entry, a^{n+1} on exit.  Returns the
+    tree handle (reuse it for the next step)."""
+    pos, mass = _check_particles(pos, mass)
+    if not (vel.is_contiguous() and pos.is_contiguous() and acc.is_contiguous()):
+        raise ValueError("pos, vel and acc must be contiguous (they are updated in place)")
+    if vel.shape != pos.shape or vel.dtype != pos.dtype or vel.device != pos.device:
+        raise ValueError("vel must match pos")
+    adt = torch.float32 if walk == "f32c" else torch.float64
+    if acc.dtype != adt or acc.shape != pos.shape:
+        raise ValueError("acc must be [n,3] of the walk precision")
+    t = tree if tree is not None else Tree()
+    t.device = pos.device
+    t.n = pos.shape[0]
+    with torch.cuda.device(pos.device):
+        check(t._lib.tc_leapfrog_step(ctypes.byref(t._h), _ptr(pos), _ptr(vel), _ptr(mass), _ptr(acc), _ptr(pot),
+                                      t.n, _DT[pos.dtype], float(tau), float(theta), float(eps), float(G),
+                                      _WALKS[walk], _stream_ptr(pos.device)))
+    t._walk = walk
+    t._keep = (pos, mass)
+    return t
 
 
 def forces(pos, mass, theta, eps, G=1.0, walk="f32c", count=False, tree=None):

@@ -1,0 +1,170 @@
+"""GPU parity of the adjoint walk (tc_forces_backward, TreeForces) and the
+leapfrog step (tc_leapfrog_step) against the FP64 oracle.
+
+Bars: FP64 walk — gradients within 1e-12 (median) / 1e-10 (p99) of the
+oracle's frozen-list adjoint; compensated-FP32 walk — within 1e-5 / 1e-4
+(relative, per particle, vector norm for dL/dx); leapfrog with the FP64
+walk on FP64 data — positions and velocities within 1e-13 of the oracle's
+step; FP32 data — the kick and drift reproduce the FP64-then-round
+arithmetic exactly, and the new forces match the oracle evaluated at the
+GPU's new positions within the walk's bar.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.atleast_2d(a.T).T, np.atleast_2d(b.T).T
+    return np.linalg.norm(a - b, axis=-1) / np.maximum(np.linalg.norm(b, axis=-1), 1e-300)
+
+
+def _case(n, seed, dtype=np.float64):
+    x, m = workloads.plummer(n, seed)
+    m = m * (1.0 + 0.3 * np.sin(np.arange(n)))
+    g = np.random.default_rng(seed + 1).standard_normal((n, 3))
+    h = np.random.default_rng(seed + 2).standard_normal(n)
+    return x.astype(dtype), m.astype(dtype), g, h
+
+
+@pytest.mark.parametrize("walk", ["f64", "f32c"])
+@pytest.mark.parametrize("theta", [0.0, 0.6])
+def test_backward_matches_oracle_adjoint(walk, theta):
+    import paper_2412_01733_amd as tc
+    n, eps = 6000, 0.01
+    x, m, g, h = _case(n, 61)
+    print("adjoint case", walk, theta, flush=True)
+    T = oracle.Tree(x, m)
+    L = T.lists(theta)
+    gx_ref, gm_ref = T.frozen_adjoint(L, eps, g, h)
+    t = tc.Tree()
+    t.build(torch.from_numpy(x).to(dev()), torch.from_numpy(m).to(dev())).moments()
+    t.forces(theta, eps, walk=walk, count=True)
+    dt = torch.float64 if walk == "f64" else torch.float32
+    gpos, gmass = t.backward(torch.from_numpy(g).to(dev(), dt), torch.from_numpy(h).to(dev(), dt))
+    torch.cuda.synchronize()
+    gpos, gmass = gpos.double().cpu().numpy(), gmass.double().cpu().numpy()
+    counts = t.interaction_counts().cpu().numpy()
+    same = counts == np.diff(L[0])  # targets whose interaction set the GPU reproduced
+    ex, em = rel(gpos, gx_ref), np.abs(gmass - gm_ref) / np.abs(gm_ref)
+    med, p99 = (1e-12, 1e-10) if walk == "f64" else (1e-5, 1e-4)
+    assert np.median(ex) <= med and np.quantile(ex, 0.99) <= p99, (np.median(ex), np.quantile(ex, 0.99))
+    assert np.median(em) <= med and np.quantile(em, 0.99) <= p99, (np.median(em), np.quantile(em, 0.99))
+    assert same.mean() > 0.99
+
+
+def test_treeforces_gradcheck_fp64():
+    import paper_2412_01733_amd as tc
+    x, m, _, _ = _case(40, 71)
+    pos = torch.from_numpy(x).to(dev()).requires_grad_(True)
+    mass = torch.from_numpy(m).to(dev()).requires_grad_(True)
+
+    def f(p, mm):
+        a, phi = tc.TreeForces.apply(p, mm, 0.7, 0.05, 1.0, "f64")
+        return a, phi
+
+    assert torch.autograd.gradcheck(f, (pos, mass), eps=1e-7, atol=1e-7, rtol=1e-6)
+
+
+def test_treeforces_loss_gradient_matches_finite_differences_fp32():
+    """The fitting use case: L = mean |a - a*|^2, FP32 walk, against FP64
+    central differences of the oracle's frozen-list evaluation."""
+    import paper_2412_01733_amd as tc
+    n, eps, theta = 4096, 0.01, 0.5
+    x, m = workloads.plummer(n, 81, dtype=np.float32)
+    m_true = np.full(n, 1.0 / n, np.float32)
+    astar, _, _ = oracle.forces(x, m_true, theta, eps)
+    m_pert = (workloads.lognormal_masses(n, 82)).astype(np.float32)
+    pos = torch.from_numpy(x).to(dev()).requires_grad_(True)
+    mass = torch.from_numpy(m_pert).to(dev()).requires_grad_(True)
+    a, _ = tc.TreeForces.apply(pos, mass, theta, eps, 1.0, "f32c")
+    loss = ((a.double() - torch.from_numpy(astar).to(dev())) ** 2).sum() / n
+    loss.backward()
+    gx, gm = pos.grad.double().cpu().numpy(), mass.grad.double().cpu().numpy()
+    T = oracle.Tree(x, m_pert)
+    L = T.lists(theta)
+    xd, md = x.astype(np.float64), m_pert.astype(np.float64)
+
+    def lossf(xx, mm):
+        aa, _ = T.frozen_forces(xx, mm, L, eps)
+        return ((aa - astar) ** 2).sum() / n
+
+    rng = np.random.default_rng(3003)
+    for c in rng.choice(4 * n, size=64, replace=False):
+        i, k = divmod(int(c), 4)
+        if k < 3:
+            hh = 1e-6
+            xp, xm = xd.copy(), xd.copy()
+            xp[i, k] += hh
+            xm[i, k] -= hh
+            fd = (lossf(xp, md) - lossf(xm, md)) / (2 * hh)
+            got, scale = gx[i, k], np.abs(gx).max()
+        else:
+            hh = 1e-6 * md[i]
+            mp, mm = md.copy(), md.copy()
+            mp[i] += hh
+            mm[i] -= hh
+            fd = (lossf(xd, mp) - lossf(xd, mm)) / (2 * hh)
+            got, scale = gm[i], np.abs(gm).max()
+        assert abs(got - fd) <= 1e-4 * max(abs(fd), 1e-2 * scale), (c, got, fd)
+
+
+def test_leapfrog_fp64_matches_oracle_step():
+    import paper_2412_01733_amd as tc
+    n = 3000
+    x, m = workloads.plummer(n, 91)
+    v = np.random.default_rng(92).standard_normal((n, 3)) * 0.3
+    a0, _, _ = oracle.forces(x, m, 0.6, 0.01)
+    ref = (x, v, a0)
+    px, pv, pa = (torch.from_numpy(np.ascontiguousarray(q)).to(dev()) for q in (x, v, a0))
+    pm = torch.from_numpy(m).to(dev())
+    pot = torch.empty(n, dtype=torch.float64, device=dev())
+    t = None
+    for step in range(3):
+        ref = oracle.leapfrog_step(ref[0], ref[1], m, ref[2], 1e-3, 0.6, 0.01)
+        t = tc.leapfrog_step(px, pv, pm, pa, 1e-3, 0.6, 0.01, walk="f64", pot=pot, tree=t)
+    torch.cuda.synchronize()
+    assert np.abs(px.cpu().numpy() - ref[0]).max() <= 1e-13
+    assert np.abs(pv.cpu().numpy() - ref[1]).max() <= 1e-12
+    assert rel(pa.cpu().numpy(), ref[2]).max() <= 1e-10
+    st = t.stats()
+    xs, vs, ps = px.cpu().numpy(), pv.cpu().numpy(), pot.cpu().numpy()
+    ke = 0.5 * (m * (vs * vs).sum(1)).sum()
+    pe = 0.5 * (m * ps).sum()
+    assert abs(st["kinetic"] / ke - 1) < 1e-12 and abs(st["potential"] / pe - 1) < 1e-12
+    assert np.allclose(st["lin_momentum"], (m[:, None] * vs).sum(0), rtol=1e-10, atol=1e-14)
+    assert np.allclose(st["ang_momentum"], (m[:, None] * np.cross(xs, vs)).sum(0), rtol=1e-10, atol=1e-14)
+
+
+def test_leapfrog_fp32_disc_step_parity():
+    import paper_2412_01733_amd as tc
+    x, v, m = workloads.disc_galaxy(8000, 2000, 1001)
+    x, v, m = x.astype(np.float32), v.astype(np.float32), m.astype(np.float32)
+    theta, eps, tau = 0.5, 0.02, 1e-3
+    a0 = tc.forces(torch.from_numpy(x).to(dev()), torch.from_numpy(m).to(dev()), theta, eps)[0]
+    px, pv = torch.from_numpy(x.copy()).to(dev()), torch.from_numpy(v.copy()).to(dev())
+    pm = torch.from_numpy(m).to(dev())
+    pa = a0.clone()
+    a_in = a0.cpu().numpy().astype(np.float64)
+    tc.leapfrog_step(px, pv, pm, pa, tau, theta, eps, walk="f32c")
+    torch.cuda.synchronize()
+    # the kick and the drift: FP64 arithmetic rounded to the FP32 storage
+    vh = (v.astype(np.float64) + 0.5 * tau * a_in).astype(np.float32)
+    xn = (x.astype(np.float64) + tau * vh.astype(np.float64)).astype(np.float32)
+    assert (px.cpu().numpy() == xn).all()
+    # the forces at the new positions, against the oracle fed the GPU's positions
+    ar, _, _ = oracle.forces(xn, m, theta, eps)
+    e = rel(pa.cpu().numpy().astype(np.float64), ar)
+    assert np.median(e) <= 1e-5 and np.quantile(e, 0.99) <= 1e-4
+    vn = (vh.astype(np.float64) + 0.5 * tau * pa.cpu().numpy().astype(np.float64)).astype(np.float32)
+    assert (pv.cpu().numpy() == vn).all()
