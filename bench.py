@@ -14,6 +14,8 @@ Prints one JSON line.  Options:
   --steps K       timed steps per walk (default 10)
   --warmup W      untimed steps per walk (default 3)
   --no-cpu        skip the oracle leg (CPU baseline + accuracy)
+  --no-adjoint    skip the fwd+adjoint leg (Plummer N = 2^18, log-normal masses)
+  --mode M        headline (default) | nscan | disc100m | kdk | host-scaling (see bench_modes.py)
   --calib-copy    also run a device copy of 1 GiB (calibrates rocprofv3 byte counters)
 """
 from __future__ import annotations
@@ -32,9 +34,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FLOPS_PER_INTERACTION = 20          # acc + pot, rsqrt counted as one
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_f32c_plummer1e7_traffic.txt")
+WALK_SRC = os.path.join(ROOT, "paper_2412_01733_amd", "csrc", "walk.hip")
 PEAK_FP32_TFLOPS = 157.3             # MI355X FP32 vector (packed FMA)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6    # one FMA per lane per clock: 256 CU x 64 lanes x 2 x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
+
+
+def walk_traffic_bytes():
+    """HBM bytes per walk launch from the committed rocprofv3 counter summary,
+    or None if the walk source changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(WALK_SRC, "rb").read()).hexdigest()
+        if kv.get("walk_hip_sha256") != sha:
+            return None
+        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
+        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+        return (fetch + write) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def sem(x):
@@ -46,6 +70,50 @@ def sem(x):
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def adjoint_leg(tc, workloads, torch, dev, args):
+    """fwd+adjoint ms against forward-only ms: Plummer N = 2^18, masses
+    perturbed log-normally (sigma = 0.2), loss = mean |a - a*|^2 with a* the
+    field of the unperturbed masses, theta = 0.5, eps = 0.01, FP32 walk."""
+    n, theta, eps = 1 << 18, 0.5, 0.01
+    pos_np, _ = workloads.plummer(n, 1003, dtype=np.float32)
+    m_np = workloads.lognormal_masses(n, 2003).astype(np.float32)
+    pos = torch.from_numpy(pos_np).to(dev)
+    m_true = torch.full((n,), 1.0 / n, dtype=torch.float32, device=dev)
+    mass = torch.from_numpy(m_np).to(dev)
+    tree = tc.Tree()
+    astar, _ = tree.build(pos, m_true).moments().forces(theta, eps, walk="f64")
+    astar = astar.float()
+
+    def fwd():
+        tree.build(pos, mass).moments()
+        a, _ = tree.forces(theta, eps, walk="f32c")
+        return a
+
+    def fwd_adj():
+        a = fwd()
+        g = (2.0 / n) * (a - astar)
+        return tree.backward(g, None)
+
+    res = {}
+    for name, fn in (("fwd", fwd), ("fwd_adj", fwd_adj)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) * 1e3 / args.steps
+    tree.set_timing(True)
+    fwd_adj()
+    st = tree.stats()
+    tree.set_timing(False)
+    log("bench: adjoint leg N=%d: fwd %.3f ms, fwd+adjoint %.3f ms" % (n, res["fwd"], res["fwd_adj"]))
+    return dict(workload="plummer-N262144-lognormal-masses-theta0.5-eps0.01", n=n, walk="f32c",
+                fwd_ms=res["fwd"], fwd_adj_ms=res["fwd_adj"], ratio=res["fwd_adj"] / res["fwd"],
+                bwd_walk_ms=st["stage_ms"][6], bwd_down_ms=st["stage_ms"][7], fwd_walk_ms=st["stage_ms"][4])
 
 
 def main():
@@ -62,7 +130,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 18)
     ap.add_argument("--acc-sample", type=int, default=1 << 16)
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--mode", default="headline", choices=["headline", "nscan", "disc100m", "kdk", "host-scaling"])
     args = ap.parse_args()
+    if args.mode != "headline":
+        import bench_modes
+        return bench_modes.run(args)
 
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the TreeCode path here is a single-GPU build "
@@ -147,6 +220,10 @@ def main():
         log("bench: %s step %.3f ms (walk %.3f ms) -> %.4g particle-forces/s" %
             (walk, total_ms, walk_ms.mean(), n / (total_ms * 1e-3)))
 
+    adj = None
+    if not args.no_adjoint:
+        adj = adjoint_leg(tc, workloads, torch, dev, args)
+
     out_acc = {}
     cpu = None
     if not args.no_cpu:
@@ -199,12 +276,13 @@ def main():
         "config": {"workload": "plummer-N%d-theta%g-eps%g" % (n, args.theta, args.eps), "n": n,
                    "theta": args.theta, "eps": args.eps, "walk": head, "inputs": "fp32, seed %d" % args.seed},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": walk_traffic_bytes() if head == "f32c" else None,
                      "kernel": "k_walk<%s>" % ("F32C" if head == "f32c" else "F64"),
                      "flops_per_interaction": FLOPS_PER_INTERACTION, "interactions": r["interactions"],
                      "walk_ms": r["walk_ms"],
                      "frac_nonpacked_fp32": (achieved / PEAK_FP32_NONPACKED_TFLOPS) if head == "f32c" else None},
         "cpu_baseline": cpu,
+        "adjoint": adj,
         "walks": {},
         "accuracy_vs_oracle": out_acc,
     }
