@@ -136,6 +136,42 @@ __device__ inline void wave_sum4(R& a0, R& a1, R& a2, R& a3)
     }
 }
 
+// Sum over each 16-lane row of the wave (DPP: xor 1, xor 2, half-row
+// mirror, row mirror); afterwards every lane holds its row's sum.
+__device__ inline float dpp_f(float v, int ctrl)
+{
+    switch (ctrl) {  // the control word must be a constant
+    case 0: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+    case 1: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+    case 2: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+    default: return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
+    }
+}
+
+__device__ inline double dpp_d(double v, int ctrl)
+{
+    const long long b = __double_as_longlong(v);
+    int lo = (int)(b & 0xFFFFFFFF), hi = (int)(b >> 32);
+    switch (ctrl) {
+    case 0: lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false); break;
+    case 1: lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false); break;
+    case 2: lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false); break;
+    default: lo = __builtin_amdgcn_mov_dpp(lo, 0x140, 0xF, 0xF, false); hi = __builtin_amdgcn_mov_dpp(hi, 0x140, 0xF, 0xF, false); break;
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename R>
+__device__ inline R row_sum(R v)
+{
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if constexpr (sizeof(R) == 8) v += dpp_d(v, c);
+        else v += dpp_f(v, c);
+    }
+    return v;
+}
+
 __device__ inline void add4(double* dst, double v0, double v1, double v2, double v3)
 {
     unsafeAtomicAdd(dst + 0, v0);
@@ -157,6 +193,8 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     __shared__ StackEntry stk[kWalkWaves][kStack];
     __shared__ Hot stg[kWalkWaves][8];
     __shared__ uint32_t stg_meta[kWalkWaves][8];
+    // adjoint: per staged child, the 4 row partials of (dL/dX, dL/dM)
+    __shared__ R rowp[ADJ ? kWalkWaves : 1][8][4][4];
     R tau0;
     if constexpr (F64) tau0 = a.tau0_64;
     else tau0 = a.tau0_32;
@@ -248,6 +286,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
             vis_nodes += nc;
             vis_lanes += (uint64_t)nc * (uint64_t)__popcll(mask);
         }
+        uint32_t src_m = 0;  // adjoint: children with at least one accepting lane
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             if ((uint32_t)k >= nc) break;
@@ -279,8 +318,16 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                         by -= sy0;
                         bz -= sz0;
                     }
-                    wave_sum4(sx0, sy0, sz0, sm0);
-                    if (lane == 0) add4(a.node_grad + 4 * (int64_t)(gs + k), sx0, sy0, sz0, sm0);
+                    // source side: sum over each row now, over the 4 rows after the group
+                    sx0 = row_sum(sx0);
+                    sy0 = row_sum(sy0);
+                    sz0 = row_sum(sz0);
+                    sm0 = row_sum(sm0);
+                    if ((lane & 15) == 0) {
+                        R* rp = &rowp[w][k][lane >> 4][0];
+                        rp[0] = sx0; rp[1] = sy0; rp[2] = sz0; rp[3] = sm0;
+                    }
+                    src_m |= 1u << k;
                 }
             }
             const uint64_t om = mask & ~am;
@@ -332,6 +379,18 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
             }
         }
         wave_sync();
+        if constexpr (ADJ) {
+            // one FP64 atomic per (child, component): lane = 4 k + component
+            if (src_m) {
+                const uint32_t k = lane >> 2, c = lane & 3;
+                if (lane < 32 && ((src_m >> k) & 1u)) {
+                    const double v = (double)rowp[w][k][0][c] + (double)rowp[w][k][1][c] +
+                                     (double)rowp[w][k][2][c] + (double)rowp[w][k][3][c];
+                    unsafeAtomicAdd(a.node_grad + 4 * (int64_t)(gs + k) + c, v);
+                }
+                wave_sync();
+            }
+        }
         if (++since_flush == kFlushEvery || sp == 0) {
             since_flush = 0;
             if constexpr (F64) {
