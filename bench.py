@@ -15,7 +15,7 @@ Prints one JSON line.  Options:
   --warmup W      untimed steps per walk (default 3)
   --no-cpu        skip the oracle leg (CPU baseline + accuracy)
   --no-adjoint    skip the fwd+adjoint leg (Plummer N = 2^18, log-normal masses)
-  --mode M        headline (default) | nscan | disc100m | kdk | host-scaling (see bench_modes.py)
+  --mode M        headline (default) | precision | nscan | disc100m | kdk | host-scaling (see bench_modes.py)
   --calib-copy    also run a device copy of 1 GiB (calibrates rocprofv3 byte counters)
 """
 from __future__ import annotations
@@ -59,6 +59,55 @@ def walk_traffic_bytes():
         return (fetch + write) * 1024.0
     except (OSError, KeyError, ValueError):
         return None
+
+
+PEAK_HBM_GBPS = 8000.0               # MI355X HBM3E
+
+
+def stage_bytes(n, nn, p=4):
+    """Compulsory HBM bytes of each build stage: what its kernels read and
+    write once (no re-reads), for n particles, nn nodes and p-byte inputs."""
+    keys = n * (4 * p + (4 * p + 8 + 4 + 4 * p))            # bounds; keys + index + packed record
+    sort = n * (8 * (8 + 24) + (4 + 4 * p + 32))             # 8 radix passes (count + move); gather
+    tree = n * (9 + 5 + 8 + 13) + nn * (13 + 13 + 13 + 32 + 8 + 33)
+    moments = n * 32 + nn * (16 + 32 + 4 + 32)
+    return dict(keys=keys, sort=sort, tree=tree, moments=moments)
+
+
+def copy_bandwidth(torch, dev):
+    """Device-to-device copy of 1 GiB: (read + write bytes) / time, GB/s."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del a, b
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def gpu_clocks():
+    """Current shader and memory clock levels of the visible cards, read from
+    the driver's sysfs tables (the active level is marked '*'); None if the
+    tables are not readable."""
+    import glob
+    out = {}
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        card = {}
+        for kind in ("sclk", "mclk"):
+            try:
+                for line in open(os.path.join(dev, "pp_dpm_" + kind)):
+                    if line.rstrip().endswith("*"):
+                        card[kind] = line.split(":", 1)[1].strip(" *\n")
+            except OSError:
+                pass
+        if card:
+            out[os.path.basename(os.path.dirname(dev))] = card
+    return out or None
 
 
 def sem(x):
@@ -131,7 +180,7 @@ def main():
     ap.add_argument("--acc-sample", type=int, default=1 << 16)
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--mode", default="headline", choices=["headline", "nscan", "disc100m", "kdk", "host-scaling"])
+    ap.add_argument("--mode", default="headline", choices=["headline", "precision", "nscan", "disc100m", "kdk", "host-scaling"])
     args = ap.parse_args()
     if args.mode != "headline":
         import bench_modes
@@ -257,6 +306,13 @@ def main():
 
     head = walks[0]
     r = res[head]
+    sb = stage_bytes(n, r["n_nodes"])
+    hbm = {}
+    for k, b in sb.items():
+        ms = r["stage_ms"][k]
+        gbps = b / (ms * 1e-3) / 1e9 if ms > 0 else None
+        hbm[k] = dict(bytes=int(b), ms=ms, GBps=gbps, frac=(gbps / PEAK_HBM_GBPS) if gbps else None)
+    copy_gbps = copy_bandwidth(torch, dev)
     flops = FLOPS_PER_INTERACTION * r["interactions"]
     achieved = flops / (r["walk_ms"] * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if head == "f32c" else PEAK_FP64_TFLOPS
@@ -281,6 +337,9 @@ def main():
                      "flops_per_interaction": FLOPS_PER_INTERACTION, "interactions": r["interactions"],
                      "walk_ms": r["walk_ms"],
                      "frac_nonpacked_fp32": (achieved / PEAK_FP32_NONPACKED_TFLOPS) if head == "f32c" else None},
+        "build_hbm": {"peak_GBps": PEAK_HBM_GBPS, "copy_GBps": copy_gbps, "stages": hbm,
+                      "note": "compulsory bytes per stage (see stage_bytes) over the stage's HIP-event time"},
+        "gpu_clocks": gpu_clocks(),
         "cpu_baseline": cpu,
         "adjoint": adj,
         "walks": {},

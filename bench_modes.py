@@ -11,6 +11,12 @@
   kdk           disc (8e5) + halo (2e5), FP32, theta = 0.5, eps = 0.02,
                 tau = 1e-3: 10 kick-drift-kick steps with a rebuild every step,
                 per-step time (mean +- SEM, Eq.(8)) and FP64 energy / momentum.
+  precision     Plummer N = 1e7, FP32 storage, eps = 0.005, theta in {0.3, 0.5,
+                0.8}: compensated-FP32 walk and plain-FP64 walk against the FP64
+                oracle on 2^16 seeded targets (median / p99 relative error of
+                acceleration and potential, interaction-count mismatches), the
+                momentum ratio R_P = |sum m a| / sum m |a| of each walk over all N,
+                and walk and step times.
   host-scaling  the oracle's own parallel efficiency on the host cores, the
                 paper's measurement method: T(M) over 10 repetitions (mean +- SEM,
                 Eq.(8)), S(M) = T(1)/T(M), E(M) = S/M and E^(P)(M) = T(1)/(T(M) M_P)
@@ -167,6 +173,64 @@ def run_kdk(args):
                 diagnostics=diag)
 
 
+def run_precision(args):
+    import torch
+    import oracle
+    import paper_2412_01733_amd as tc
+    import workloads
+    dev = torch.device("cuda:0")
+    n, eps, seed = 10_000_000, 0.005, 1002
+    pos, m = workloads.plummer(n, seed, dtype=np.float32)
+    p, mm = torch.from_numpy(pos).to(dev), torch.from_numpy(m).to(dev)
+    tree = tc.Tree()
+    tg = workloads.target_sample(n, 1 << 16, 2002)
+    sel = torch.from_numpy(tg).to(dev)
+    log("precision: oracle build at N=1e7 (1 thread) ...")
+    T = oracle.Tree(pos, m)
+    threads = min(16, os.cpu_count() or 1)
+    rows = []
+    for theta in (0.3, 0.5, 0.8):
+        ra, rp, rn = T.forces(theta, eps, targets=tg, nthreads=threads)
+        row = dict(theta=theta, oracle_interactions_per_target=float(rn.mean()), walks={})
+        for walk in ("f32c", "f64"):
+            dt = torch.float32 if walk == "f32c" else torch.float64
+            acc = torch.empty((n, 3), dtype=dt, device=dev)
+            pot = torch.empty(n, dtype=dt, device=dev)
+            tree.build(p, mm).moments()
+            tree.forces(theta, eps, walk=walk, count=True, out=(acc, pot))
+            st = tree.stats()
+            cnt = tree.interaction_counts()[sel].cpu().numpy()
+            a = acc[sel].double().cpu().numpy()
+            pp = pot[sel].double().cpu().numpy()
+            e = np.linalg.norm(a - ra, axis=1) / np.linalg.norm(ra, axis=1)
+            ep = np.abs(pp - rp) / np.abs(rp)
+
+            def step():
+                tree.build(p, mm).moments()
+                tree.forces(theta, eps, walk=walk, out=(acc, pot))
+
+            ms, ms_err = _timed(step, args.steps, args.warmup, torch)
+            tree.set_timing(True)
+            wl = []
+            for _ in range(3):
+                step()
+                wl.append(tree.stats()["stage_ms"][4])
+            tree.set_timing(False)
+            row["walks"][walk] = dict(
+                acc_median=float(np.median(e)), acc_p99=float(np.quantile(e, 0.99)),
+                pot_median=float(np.median(ep)), pot_p99=float(np.quantile(ep, 0.99)),
+                count_mismatch=float(np.mean(cnt != rn)),
+                R_P=float(np.linalg.norm(st["momentum"]) / st["sum_m_abs_a"]),
+                interactions_per_target=st["interactions"] / n,
+                step_ms=ms, step_ms_sem=ms_err, rate=n / (ms * 1e-3), walk_ms=float(np.mean(wl)),
+                walk_tflops=20 * st["interactions"] / (np.mean(wl) * 1e-3) / 1e12)
+            log("precision theta=%g %s: median %.3g p99 %.3g R_P %.3e step %.2f ms" %
+                (theta, walk, np.median(e), np.quantile(e, 0.99), row["walks"][walk]["R_P"], ms))
+        rows.append(row)
+    return dict(mode="precision", workload="plummer-N1e7-fp32-eps0.005", targets=len(tg), oracle_threads=threads,
+                rows=rows)
+
+
 def run_host_scaling(args):
     import oracle
     import workloads
@@ -210,6 +274,6 @@ def _cpu_model():
 
 
 def run(args):
-    fn = {"nscan": run_nscan, "disc100m": run_disc100m, "kdk": run_kdk, "host-scaling": run_host_scaling}[args.mode]
+    fn = {"precision": run_precision, "nscan": run_nscan, "disc100m": run_disc100m, "kdk": run_kdk, "host-scaling": run_host_scaling}[args.mode]
     out = fn(args)
     print(json.dumps(out), flush=True)

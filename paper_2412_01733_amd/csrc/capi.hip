@@ -76,7 +76,7 @@ struct tc_tree {
     tc_dtype dtype = TC_F32;
 
     // particle-sized
-    Buf keys0, keys1, vals0, vals1, sx, sy, sz, sm, c, cnt, pre, sorted_counts, diag_part;
+    Buf keys0, keys1, vals0, vals1, rec, sp, c, cnt, pre, sorted_counts, diag_part;
     uint64_t* skeys = nullptr;
     uint32_t* perm = nullptr;
     Buf sort_temp, scan_temp, bounds_part;
@@ -261,10 +261,8 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     TC_TRY(ensure(t, t->keys1, n8, s));
     TC_TRY(ensure(t, t->vals0, n4, s));
     TC_TRY(ensure(t, t->vals1, n4, s));
-    TC_TRY(ensure(t, t->sx, n8, s));
-    TC_TRY(ensure(t, t->sy, n8, s));
-    TC_TRY(ensure(t, t->sz, n8, s));
-    TC_TRY(ensure(t, t->sm, n8, s));
+    TC_TRY(ensure(t, t->rec, record_bytes(n, dt), s));
+    TC_TRY(ensure(t, t->sp, (size_t)n * sizeof(Particle), s));
     TC_TRY(ensure(t, t->c, (size_t)n, s));
     TC_TRY(ensure(t, t->cnt, n4, s));
     TC_TRY(ensure(t, t->pre, n4 + 8, s));
@@ -275,15 +273,14 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
 
     stage_begin(t, kStKeys, s);
     launch_bounds(pos, mass, n, dt, P<double>(t->bounds_part), nb, t->geom, s);
-    launch_keys(pos, n, dt, t->geom, P<uint64_t>(t->keys0), P<uint32_t>(t->vals0), s);
+    launch_keys(pos, mass, n, dt, t->geom, P<uint64_t>(t->keys0), P<uint32_t>(t->vals0), t->rec.p, s);
     stage_end(t, kStKeys, s);
     TC_TRY(check_launch("keys"));
 
     stage_begin(t, kStSort, s);
     radix_sort_pairs(P<uint64_t>(t->keys0), P<uint32_t>(t->vals0), P<uint64_t>(t->keys1), P<uint32_t>(t->vals1),
                      n, 63, t->sort_temp.p, s, &t->skeys, &t->perm);
-    launch_gather(pos, mass, n, dt, t->perm, P<double>(t->sx), P<double>(t->sy), P<double>(t->sz),
-                  P<double>(t->sm), s);
+    launch_gather(t->rec.p, n, dt, t->perm, P<Particle>(t->sp), s);
     stage_end(t, kStSort, s);
     TC_TRY(check_launch("sort"));
 
@@ -344,9 +341,8 @@ tc_status moments_impl(tc_tree* t, hipStream_t s)
     if (t->n > 0) {
         stage_begin(t, kStMoments, s);
         launch_moments(t->host->level_off, t->bfs_to_pre, P<uint32_t>(t->bfs), P<uint32_t>(t->first),
-                       P<uint32_t>(t->count), P<uint32_t>(t->nchild), t->nn, t->skeys, P<double>(t->sx),
-                       P<double>(t->sy), P<double>(t->sz), P<double>(t->sm), t->geom, P<WalkNode>(t->wn),
-                       P<uint32_t>(t->parent), s);
+                       P<uint32_t>(t->count), P<uint32_t>(t->nchild), t->skeys, P<Particle>(t->sp), t->geom,
+                       P<WalkNode>(t->wn), P<uint32_t>(t->parent), s);
         stage_end(t, kStMoments, s);
         TC_TRY(check_launch("moments"));
     }
@@ -359,10 +355,7 @@ tc_status moments_impl(tc_tree* t, hipStream_t s)
 tc_status walk_args(tc_tree* t, double theta, double eps, double G, tc_walk mode, WalkArgs& a)
 {
     a.nodes = P<WalkNode>(t->wn);
-    a.sx = P<double>(t->sx);
-    a.sy = P<double>(t->sy);
-    a.sz = P<double>(t->sz);
-    a.sm = P<double>(t->sm);
+    a.sp = P<Particle>(t->sp);
     a.perm = t->perm;
     a.n = t->n;
     a.eps2 = eps * eps;
@@ -455,7 +448,7 @@ tc_status backward_impl(tc_tree* t, const void* g_acc, const void* g_pot, void* 
     TC_TRY(check_launch("adjoint walk"));
     stage_begin(t, kStBwdDown, s);
     launch_adjoint_down(t->host->level_off, P<WalkNode>(t->wn), P<uint32_t>(t->parent), a.node_grad, P<double>(t->uc),
-                        a.sx, a.sy, a.sz, a.sm, t->perm, a.target_grad, a.part_grad, g_pos, g_mass,
+                        a.sp, t->perm, a.target_grad, a.part_grad, g_pos, g_mass,
                         t->last_mode == TC_WALK_F64, s);
     stage_end(t, kStBwdDown, s);
     TC_TRY(check_launch("adjoint down-pass"));
@@ -680,7 +673,7 @@ void tc_tree_free(tc_tree* t)
 {
     if (!t) return;
     (void)hipDeviceSynchronize();
-    Buf* bufs[] = {&t->keys0, &t->keys1, &t->vals0, &t->vals1, &t->sx, &t->sy, &t->sz, &t->sm, &t->c, &t->cnt,
+    Buf* bufs[] = {&t->keys0, &t->keys1, &t->vals0, &t->vals1, &t->rec, &t->sp, &t->c, &t->cnt,
                    &t->pre, &t->sorted_counts, &t->diag_part, &t->sort_temp, &t->scan_temp, &t->bounds_part,
                    &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->bfs, &t->nk0, &t->nk1,
                    &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->parent, &t->node_grad,

@@ -147,35 +147,64 @@ __device__ inline uint64_t quantise(double x, double lo, double scale)
     return (uint64_t)f;
 }
 
+// Packed particle record {x, y, z, m} in caller order, so that the gather
+// after the sort reads one aligned record per particle instead of four
+// scattered scalars.
+template <typename T> struct Rec;
+template <> struct Rec<float> {
+    __device__ static void put(float* r, int64_t i, float x, float y, float z, float m)
+    {
+        reinterpret_cast<float4*>(r)[i] = make_float4(x, y, z, m);
+    }
+    __device__ static void get(const float* r, int64_t i, double& x, double& y, double& z, double& m)
+    {
+        const float4 v = reinterpret_cast<const float4*>(r)[i];
+        x = v.x; y = v.y; z = v.z; m = v.w;
+    }
+};
+template <> struct Rec<double> {
+    __device__ static void put(double* r, int64_t i, double x, double y, double z, double m)
+    {
+        reinterpret_cast<double2*>(r)[2 * i] = make_double2(x, y);
+        reinterpret_cast<double2*>(r)[2 * i + 1] = make_double2(z, m);
+    }
+    __device__ static void get(const double* r, int64_t i, double& x, double& y, double& z, double& m)
+    {
+        const double2 a = reinterpret_cast<const double2*>(r)[2 * i];
+        const double2 b = reinterpret_cast<const double2*>(r)[2 * i + 1];
+        x = a.x; y = a.y; z = b.x; m = b.y;
+    }
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_keys(const T* __restrict__ pos, int64_t n,
+__global__ __launch_bounds__(256) void k_keys(const T* __restrict__ pos, const T* __restrict__ mass, int64_t n,
                                               const Geom* __restrict__ g,
                                               uint64_t* __restrict__ keys,
-                                              uint32_t* __restrict__ idx)
+                                              uint32_t* __restrict__ idx, T* __restrict__ rec)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double sc = g->scale;
-    uint64_t qx = quantise((double)pos[3 * i + 0], g->lo[0], sc);
-    uint64_t qy = quantise((double)pos[3 * i + 1], g->lo[1], sc);
-    uint64_t qz = quantise((double)pos[3 * i + 2], g->lo[2], sc);
+    const T x = pos[3 * i + 0], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    uint64_t qx = quantise((double)x, g->lo[0], sc);
+    uint64_t qy = quantise((double)y, g->lo[1], sc);
+    uint64_t qz = quantise((double)z, g->lo[2], sc);
     keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
     idx[i] = (uint32_t)i;
+    Rec<T>::put(rec, i, x, y, z, mass[i]);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ pos, const T* __restrict__ mass,
-                                                int64_t n, const uint32_t* __restrict__ perm,
-                                                double* __restrict__ sx, double* __restrict__ sy,
-                                                double* __restrict__ sz, double* __restrict__ sm)
+__global__ __launch_bounds__(256) void k_gather(const T* __restrict__ rec, int64_t n,
+                                                const uint32_t* __restrict__ perm, Particle* __restrict__ sp)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const int64_t i = perm[s];
-    sx[s] = (double)pos[3 * i + 0];
-    sy[s] = (double)pos[3 * i + 1];
-    sz[s] = (double)pos[3 * i + 2];
-    sm[s] = (double)mass[i];
+    double x, y, z, m;
+    Rec<T>::get(rec, perm[s], x, y, z, m);
+    double2* o = reinterpret_cast<double2*>(sp + s);
+    o[0] = make_double2(x, y);
+    o[1] = make_double2(z, m);
 }
 
 inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
@@ -202,26 +231,27 @@ void launch_bounds(const void* pos, const void* mass, int64_t n, tc_dtype dt, do
     k_bounds_final<<<1, kBoundsThreads, 0, s>>>(partials, nblocks, n, geom);
 }
 
-void launch_keys(const void* pos, int64_t n, tc_dtype dt, const Geom* geom, uint64_t* keys,
-                 uint32_t* idx, hipStream_t s)
+size_t record_bytes(int64_t n, tc_dtype dt) { return (size_t)n * 4 * (dt == TC_F32 ? sizeof(float) : sizeof(double)); }
+
+void launch_keys(const void* pos, const void* mass, int64_t n, tc_dtype dt, const Geom* geom, uint64_t* keys,
+                 uint32_t* idx, void* rec, hipStream_t s)
 {
     if (n == 0) return;
     if (dt == TC_F32)
-        k_keys<float><<<grid_for(n, 256), 256, 0, s>>>((const float*)pos, n, geom, keys, idx);
+        k_keys<float><<<grid_for(n, 256), 256, 0, s>>>((const float*)pos, (const float*)mass, n, geom, keys, idx,
+                                                       (float*)rec);
     else
-        k_keys<double><<<grid_for(n, 256), 256, 0, s>>>((const double*)pos, n, geom, keys, idx);
+        k_keys<double><<<grid_for(n, 256), 256, 0, s>>>((const double*)pos, (const double*)mass, n, geom, keys,
+                                                        idx, (double*)rec);
 }
 
-void launch_gather(const void* pos, const void* mass, int64_t n, tc_dtype dt, const uint32_t* perm,
-                   double* sx, double* sy, double* sz, double* sm, hipStream_t s)
+void launch_gather(const void* rec, int64_t n, tc_dtype dt, const uint32_t* perm, Particle* sp, hipStream_t s)
 {
     if (n == 0) return;
     if (dt == TC_F32)
-        k_gather<float><<<grid_for(n, 256), 256, 0, s>>>((const float*)pos, (const float*)mass, n, perm,
-                                                         sx, sy, sz, sm);
+        k_gather<float><<<grid_for(n, 256), 256, 0, s>>>((const float*)rec, n, perm, sp);
     else
-        k_gather<double><<<grid_for(n, 256), 256, 0, s>>>((const double*)pos, (const double*)mass, n,
-                                                          perm, sx, sy, sz, sm);
+        k_gather<double><<<grid_for(n, 256), 256, 0, s>>>((const double*)rec, n, perm, sp);
 }
 
 }  // namespace tc

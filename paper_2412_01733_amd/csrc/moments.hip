@@ -1,16 +1,17 @@
 // Upward pass: monopole moments of every node (TreeCode description of
 // section 2: a distant cell acts as its total mass at its centre of mass).
 //
-// One launch per level, deepest first, over that level's contiguous range of
-// the breadth-first node array, so a parent reads finished children, which
-// are consecutive records.
+// Level by level, deepest first, over that level's contiguous range of the
+// breadth-first node array, so a parent reads finished children, which are
+// consecutive records: one launch per populous level, one single-workgroup
+// launch per run of small levels.
 // Everything is FP64 with no FMA contraction, summed in a fixed order
 // (particles in key order inside a leaf, children in octant order), so the
 // result does not depend on scheduling:
 //   leaf of one particle:  M = m_j, X = x_j exactly;
 //   otherwise:             M = sum M_c, X = (sum M_c X_c) / M,
 //                          X = the cell centre when M = 0.
-// The same launch writes the node's whole walk record.
+// The same pass writes the node's whole walk record.
 #include "tc_internal.h"
 
 namespace tc {
@@ -37,53 +38,34 @@ __device__ inline void cell_centre(uint64_t key, int level, const Geom* g, doubl
     }
 }
 
-__global__ __launch_bounds__(256) void k_moments_level(
-    int l, uint32_t b0, uint32_t b1, const uint32_t* __restrict__ bfs_to_pre, const uint32_t* __restrict__ bfs,
-    const uint32_t* __restrict__ first, const uint32_t* __restrict__ count, const uint32_t* __restrict__ nchild,
-    int64_t nn, const uint64_t* __restrict__ skeys, const double* __restrict__ sx, const double* __restrict__ sy,
-    const double* __restrict__ sz, const double* __restrict__ sm, const Geom* __restrict__ g,
-    WalkNode* __restrict__ wn, uint32_t* __restrict__ parent)
+// One node, at breadth-first position b (pre-order index p).
+__device__ inline void moments_node(int64_t b, int l, const uint32_t* __restrict__ bfs_to_pre,
+                                    const uint32_t* __restrict__ bfs, const uint32_t* __restrict__ first,
+                                    const uint32_t* __restrict__ count, const uint32_t* __restrict__ nchild,
+                                    const uint64_t* __restrict__ skeys, const Particle* __restrict__ sp,
+                                    const Geom* __restrict__ g, WalkNode* __restrict__ wn,
+                                    uint32_t* __restrict__ parent)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t b = (int64_t)b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < (int64_t)b1; b += stride) {
-        const uint32_t p = bfs_to_pre[b];
-        const uint32_t f = first[p], c = count[p], nc = nchild[p];
-        double M = 0.0, X[3];
-        bool centre = false;
-        uint32_t child = 0;
-        if (nc == 0) {
-            if (c == 1) {
-                M = sm[f];
-                X[0] = sx[f];
-                X[1] = sy[f];
-                X[2] = sz[f];
-            } else {
-                double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-                for (uint32_t j = f; j < f + c; ++j) {
-                    const double mj = sm[j];
-                    M += mj;
-                    S0 += mj * sx[j];
-                    S1 += mj * sy[j];
-                    S2 += mj * sz[j];
-                }
-                if (M == 0.0) centre = true;
-                else {
-                    X[0] = S0 / M;
-                    X[1] = S1 / M;
-                    X[2] = S2 / M;
-                }
-            }
+    const uint32_t p = bfs_to_pre[b];
+    const uint32_t f = first[p], c = count[p], nc = nchild[p];
+    double M = 0.0, X[3];
+    bool centre = false;
+    uint32_t child = 0;
+    if (nc == 0) {
+        if (c == 1) {
+            const Particle q = sp[f];
+            M = q.m;
+            X[0] = q.x;
+            X[1] = q.y;
+            X[2] = q.z;
         } else {
-            child = bfs[p + 1];  // the first child follows its parent in pre-order
             double S0 = 0.0, S1 = 0.0, S2 = 0.0;
-            for (uint32_t k = 0; k < nc; ++k) {
-                parent[child + k] = (uint32_t)b;
-                const WalkNode& ch = wn[child + k];
-                const double mc = ch.m;
-                M += mc;
-                S0 += mc * ch.x;
-                S1 += mc * ch.y;
-                S2 += mc * ch.z;
+            for (uint32_t j = f; j < f + c; ++j) {
+                const Particle q = sp[j];
+                M += q.m;
+                S0 += q.m * q.x;
+                S1 += q.m * q.y;
+                S2 += q.m * q.z;
             }
             if (M == 0.0) centre = true;
             else {
@@ -92,17 +74,59 @@ __global__ __launch_bounds__(256) void k_moments_level(
                 X[2] = S2 / M;
             }
         }
-        if (centre) cell_centre(skeys[f], l, g, X);
-        WalkNode r;
-        r.x = X[0];
-        r.y = X[1];
-        r.z = X[2];
-        r.m = M;
-        r.first = f;
-        r.count = c;
-        r.child = child;
-        r.meta = nc | ((uint32_t)l << 8) | (nc == 0 ? (1u << 16) : 0u) | (nc == 0 && c == 1 ? (1u << 17) : 0u);
-        wn[b] = r;
+    } else {
+        child = bfs[p + 1];  // the first child follows its parent in pre-order
+        double S0 = 0.0, S1 = 0.0, S2 = 0.0;
+        for (uint32_t k = 0; k < nc; ++k) {
+            parent[child + k] = (uint32_t)b;
+            const double2 xy = *reinterpret_cast<const double2*>(&wn[child + k].x);
+            const double2 zm = *reinterpret_cast<const double2*>(&wn[child + k].z);
+            const double mc = zm.y;
+            M += mc;
+            S0 += mc * xy.x;
+            S1 += mc * xy.y;
+            S2 += mc * zm.x;
+        }
+        if (M == 0.0) centre = true;
+        else {
+            X[0] = S0 / M;
+            X[1] = S1 / M;
+            X[2] = S2 / M;
+        }
+    }
+    if (centre) cell_centre(skeys[f], l, g, X);
+    const uint32_t meta = nc | ((uint32_t)l << 8) | (nc == 0 ? (1u << 16) : 0u) | (nc == 0 && c == 1 ? (1u << 17) : 0u);
+    uint4* o = reinterpret_cast<uint4*>(wn + b);
+    o[0] = make_uint4(__double2loint(X[0]), __double2hiint(X[0]), __double2loint(X[1]), __double2hiint(X[1]));
+    o[1] = make_uint4(__double2loint(X[2]), __double2hiint(X[2]), __double2loint(M), __double2hiint(M));
+    o[2] = make_uint4(f, c, child, meta);
+}
+
+#define MOM_ARGS                                                                                                  \
+    const uint32_t *__restrict__ bfs_to_pre, const uint32_t *__restrict__ bfs, const uint32_t *__restrict__ first, \
+        const uint32_t *__restrict__ count, const uint32_t *__restrict__ nchild, const uint64_t *__restrict__ skeys, \
+        const Particle *__restrict__ sp, const Geom *__restrict__ g, WalkNode *__restrict__ wn,                  \
+        uint32_t *__restrict__ parent
+#define MOM_PASS bfs_to_pre, bfs, first, count, nchild, skeys, sp, g, wn, parent
+
+// One level with many nodes: one thread per node.
+__global__ __launch_bounds__(256) void k_moments_level(int l, uint32_t b0, uint32_t b1, MOM_ARGS)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b = (int64_t)b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < (int64_t)b1; b += stride)
+        moments_node(b, l, MOM_PASS);
+}
+
+// A run of consecutive small levels [llo, lhi], deepest first, in one
+// workgroup: a barrier separates the levels (the waves of one workgroup share
+// a CU and its L1, so the barrier's workgroup-scope fence makes the finished
+// level visible).
+__global__ __launch_bounds__(kSmallLevelThreads) void k_moments_small(int lhi, int llo, LevelOffsets off, MOM_ARGS)
+{
+    for (int l = lhi; l >= llo; --l) {
+        for (int64_t b = (int64_t)off.off[l] + threadIdx.x; b < (int64_t)off.off[l + 1]; b += blockDim.x)
+            moments_node(b, l, MOM_PASS);
+        __syncthreads();
     }
 }
 
@@ -124,17 +148,24 @@ __global__ __launch_bounds__(256) void k_export_moments(const WalkNode* __restri
 }  // namespace
 
 void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
-                    const uint32_t* first, const uint32_t* count, const uint32_t* nchild, int64_t nn,
-                    const uint64_t* skeys, const double* sx, const double* sy, const double* sz,
-                    const double* sm, const Geom* geom, WalkNode* wn, uint32_t* parent, hipStream_t s)
+                    const uint32_t* first, const uint32_t* count, const uint32_t* nchild, const uint64_t* skeys,
+                    const Particle* sp, const Geom* g, WalkNode* wn, uint32_t* parent, hipStream_t s)
 {
-    for (int l = kMaxLevel; l >= 0; --l) {
-        const uint32_t b0 = level_off_host[l], b1 = level_off_host[l + 1];
-        if (b1 <= b0) continue;
-        int64_t blocks = ((int64_t)(b1 - b0) + 255) / 256;
+    LevelOffsets off;
+    for (int l = 0; l <= kLevels; ++l) off.off[l] = level_off_host[l];
+    int l = kMaxLevel;
+    while (l >= 0) {
+        if (off.size(l) <= kSmallLevel) {
+            int lo = l;
+            while (lo > 0 && off.size(lo - 1) <= kSmallLevel) --lo;
+            if (off.off[l + 1] > off.off[lo]) k_moments_small<<<1, kSmallLevelThreads, 0, s>>>(l, lo, off, MOM_PASS);
+            l = lo - 1;
+            continue;
+        }
+        int64_t blocks = ((int64_t)off.size(l) + 255) / 256;
         if (blocks > 8192) blocks = 8192;
-        k_moments_level<<<(unsigned)blocks, 256, 0, s>>>(l, b0, b1, bfs_to_pre, bfs, first, count, nchild, nn, skeys,
-                                                         sx, sy, sz, sm, geom, wn, parent);
+        k_moments_level<<<(unsigned)blocks, 256, 0, s>>>(l, off.off[l], off.off[l + 1], MOM_PASS);
+        --l;
     }
 }
 

@@ -38,6 +38,22 @@ struct __align__(16) WalkNode {
 };
 static_assert(sizeof(WalkNode) == 48, "WalkNode layout");
 
+// A particle in key order: position and mass, FP64 (one 32-byte record, so
+// that a leaf or a target reads one aligned line).
+struct __align__(32) Particle {
+    double x, y, z, m;
+};
+
+// Breadth-first offsets of the levels (level l occupies [off[l], off[l+1])),
+// passed by value to the level-batched kernels.  Levels with at most
+// kSmallLevel nodes are processed in runs by a single workgroup.
+struct LevelOffsets {
+    uint32_t off[kLevels + 1];
+    __host__ __device__ uint32_t size(int l) const { return off[l + 1] - off[l]; }
+};
+constexpr uint32_t kSmallLevel = 4096;
+constexpr int kSmallLevelThreads = 1024;
+
 __host__ __device__ inline uint32_t meta_nchild(uint32_t m) { return m & 0xFu; }
 __host__ __device__ inline uint32_t meta_level(uint32_t m) { return (m >> 8) & 0x1Fu; }
 __host__ __device__ inline bool meta_leaf(uint32_t m) { return (m >> 16) & 1u; }
@@ -51,10 +67,11 @@ __host__ __device__ inline bool meta_single(uint32_t m) { return (m >> 17) & 1u;
 void launch_bounds(const void* pos, const void* mass, int64_t n, tc_dtype dt, double* partials,
                    int nblocks, Geom* geom, hipStream_t s);
 int bounds_blocks(int64_t n);
-void launch_keys(const void* pos, int64_t n, tc_dtype dt, const Geom* geom, uint64_t* keys,
-                 uint32_t* idx, hipStream_t s);
-void launch_gather(const void* pos, const void* mass, int64_t n, tc_dtype dt, const uint32_t* perm,
-                   double* sx, double* sy, double* sz, double* sm, hipStream_t s);
+// keys also writes the packed {x, y, z, m} record (record_bytes) that the gather reads
+size_t record_bytes(int64_t n, tc_dtype dt);
+void launch_keys(const void* pos, const void* mass, int64_t n, tc_dtype dt, const Geom* geom, uint64_t* keys,
+                 uint32_t* idx, void* rec, hipStream_t s);
+void launch_gather(const void* rec, int64_t n, tc_dtype dt, const uint32_t* perm, Particle* sp, hipStream_t s);
 
 // scan.hip: exclusive scan, out[n] = total (out has n+1 entries)
 size_t scan_temp_bytes(int64_t n);
@@ -87,9 +104,8 @@ void launch_bfs_order(const uint8_t* level, int64_t nn, uint64_t* k0, uint32_t* 
 // moments.hip: one launch per level over the breadth-first ranges
 // [level_off_host[l], level_off_host[l+1]), deepest level first.
 void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
-                    const uint32_t* first, const uint32_t* count, const uint32_t* nchild, int64_t nn,
-                    const uint64_t* skeys, const double* sx, const double* sy, const double* sz,
-                    const double* sm, const Geom* geom, WalkNode* wn, uint32_t* parent, hipStream_t s);
+                    const uint32_t* first, const uint32_t* count, const uint32_t* nchild, const uint64_t* skeys,
+                    const Particle* sp, const Geom* geom, WalkNode* wn, uint32_t* parent, hipStream_t s);
 // Canonical export: com/mass of pre-order node p from wn[bfs[p]].
 void launch_export_moments(const WalkNode* wn, const uint32_t* bfs, int64_t nn, double* com, double* mass,
                            hipStream_t s);
@@ -97,10 +113,7 @@ void launch_export_moments(const WalkNode* wn, const uint32_t* bfs, int64_t nn, 
 // walk.hip
 struct WalkArgs {
     const WalkNode* nodes;
-    const double* sx;
-    const double* sy;
-    const double* sz;
-    const double* sm;
+    const Particle* sp;     // particles in key order
     const uint32_t* perm;
     int64_t n;
     double eps2;
@@ -126,8 +139,8 @@ void launch_walk_adjoint(const WalkArgs& a, tc_walk mode, hipStream_t s);
 
 // adjoint.hip: top-down pass from node gradients to particle gradients.
 void launch_adjoint_down(const uint32_t* level_off_host, const WalkNode* wn, const uint32_t* parent,
-                         const double* node_grad, double* uc, const double* sx, const double* sy,
-                         const double* sz, const double* sm, const uint32_t* perm, const double* target_grad,
+                         const double* node_grad, double* uc, const Particle* sp, const uint32_t* perm,
+                         const double* target_grad,
                          const double* part_grad, void* g_pos, void* g_mass, bool out_f64, hipStream_t s);
 void launch_fill_f64_zero(double* p, int64_t n, hipStream_t s);
 

@@ -210,8 +210,10 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     const uint32_t su = (uint32_t)s;
     const uint32_t wave_end = (uint32_t)(base + 64 < a.n ? base + 64 : a.n);
 
-    const double Ax = a.sx[base], Ay = a.sy[base], Az = a.sz[base];
-    const double xs = a.sx[sl], ys = a.sy[sl], zs = a.sz[sl];
+    const Particle anchor = a.sp[base];
+    const double Ax = anchor.x, Ay = anchor.y, Az = anchor.z;
+    const Particle self = a.sp[sl];
+    const double xs = self.x, ys = self.y, zs = self.z;
     R px, py, pz;
     if constexpr (F64) {
         px = xs; py = ys; pz = zs;
@@ -343,8 +345,9 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                     const uint32_t f = uni(h.first), cnt = uni(h.count);
                     const bool lane_open = (om >> lane) & 1ull;
                     for (uint32_t j = f; j < f + cnt; ++j) {
-                        const double xj = a.sx[j], yj = a.sy[j], zj = a.sz[j];
-                        const R mj = (R)a.sm[j];
+                        const Particle pj = a.sp[j];
+                        const double xj = pj.x, yj = pj.y, zj = pj.z;
+                        const R mj = (R)pj.m;
                         R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
                         if (lane_open && j != su) {
                             R ex, ey, ez;
@@ -434,7 +437,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
         acc[3 * (int64_t)i + 2] = oz;
         if (a.pot) ((R*)a.pot)[i] = op;
         if constexpr (COUNT) a.counts[s] = nint;
-        const double m = a.sm[s];
+        const double m = self.m;
         const double ex = (double)ox, ey = (double)oy, ez = (double)oz;
         dm[0] = m * ex;
         dm[1] = m * ey;

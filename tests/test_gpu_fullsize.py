@@ -1,0 +1,79 @@
+"""GPU parity at the full benchmark size: Plummer sphere, N = 1e7, FP32
+storage (seed 1002), eps = 0.005, the launch configuration the benchmark
+times (one tc_build + tc_moments + tc_forces through the C ABI).
+
+  * keys, permutation, node table and FP64 moments: bit-exact against the
+    oracle over all 1e7 particles and ~1.5e7 nodes;
+  * accelerations and potentials at theta in {0.3, 0.5, 0.8}: on 4096 seeded
+    targets the oracle evaluates one by one, F32C median <= 1e-5 and
+    p99 <= 1e-4, F64 median <= 1e-13 and p99 <= 1e-11;
+  * interaction counts on the sample: F64 differs from the oracle on at most
+    0.1% of targets, F32C on under 1% (distances within FP32 rounding of the
+    opening threshold);
+  * momentum ratio |sum m a| / sum m |a| over all N: the F32C walk within
+    1e-6 (absolute) of the F64 walk, which matches the oracle per target.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+N, SEED, EPS, SAMPLE = 10_000_000, 1002, 0.005, 4096
+
+
+@pytest.fixture(scope="module")
+def big():
+    import paper_2412_01733_amd as tc
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    print("fullsize: generating Plummer N=%d" % N, flush=True)
+    pos, m = workloads.plummer(N, SEED, dtype=np.float32)
+    dev = torch.device("cuda:0")
+    tree = tc.Tree()
+    tree.build(torch.from_numpy(pos).to(dev), torch.from_numpy(m).to(dev)).moments()
+    torch.cuda.synchronize()
+    print("fullsize: oracle build", flush=True)
+    T = oracle.Tree(pos, m)
+    tg = workloads.target_sample(N, SAMPLE, 2002)
+    return dict(pos=pos, m=m, tree=tree, T=T, tg=tg, dev=dev)
+
+
+def test_fullsize_tree_bit_exact(big):
+    ex = {k: v.cpu().numpy() for k, v in big["tree"].export(moments=True).items()}
+    T = big["T"]
+    ok, op = T.sorted()
+    assert (ex["keys"].view(np.uint64) == ok).all(), "keys differ"
+    assert (ex["perm"].astype(np.int64) == op).all(), "permutation differs"
+    nd = T.nodes()
+    assert len(ex["level"]) == len(nd["level"]), (len(ex["level"]), len(nd["level"]))
+    assert (ex["level"].astype(np.int32) == nd["level"]).all()
+    assert (ex["first"].astype(np.int64) == nd["first"]).all()
+    assert (ex["count"].astype(np.int64) == nd["count"]).all()
+    assert (ex["mass"] == nd["mass"]).all(), "moments (mass) not bit-exact"
+    assert (ex["com"] == nd["com"]).all(), "moments (com) not bit-exact"
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.8])
+def test_fullsize_sampled_forces(big, theta):
+    tree, tg = big["tree"], big["tg"]
+    ra, rp, rn = big["T"].forces(theta, EPS, targets=tg)
+    sel = torch.from_numpy(tg).to(big["dev"])
+    rp_ratio = {}
+    for walk, med, p99, flip_bar in (("f32c", 1e-5, 1e-4, 0.01), ("f64", 1e-13, 1e-11, 1e-3)):
+        print("fullsize: theta=%g walk=%s" % (theta, walk), flush=True)
+        acc, pot = tree.forces(theta, EPS, walk=walk, count=True)
+        cnt = tree.interaction_counts()[sel].cpu().numpy().astype(np.int64)
+        st = tree.stats()
+        a = acc[sel].double().cpu().numpy()
+        p = pot[sel].double().cpu().numpy()
+        e = np.linalg.norm(a - ra, axis=1) / np.linalg.norm(ra, axis=1)
+        ep = np.abs(p - rp) / np.abs(rp)
+        assert np.median(e) <= med and np.quantile(e, 0.99) <= p99, (walk, np.median(e), np.quantile(e, 0.99))
+        assert np.median(ep) <= med and np.quantile(ep, 0.99) <= p99, (walk, np.median(ep), np.quantile(ep, 0.99))
+        assert np.mean(cnt != rn) <= flip_bar, (walk, np.mean(cnt != rn))
+        rp_ratio[walk] = np.linalg.norm(st["momentum"]) / st["sum_m_abs_a"]
+    assert abs(rp_ratio["f32c"] - rp_ratio["f64"]) <= 1e-6, rp_ratio
