@@ -69,8 +69,9 @@ def stage_bytes(n, nn, p=4):
     write once (no re-reads), for n particles, nn nodes and p-byte inputs."""
     keys = n * (4 * p + (4 * p + 8 + 4 + 4 * p))            # bounds; keys + index + packed record
     sort = n * (8 * (8 + 24) + (4 + 4 * p + 32))             # 8 radix passes (count + move); gather
-    tree = n * (9 + 5 + 8 + 13) + nn * (13 + 13 + 13 + 32 + 8 + 33)
-    moments = n * 32 + nn * (16 + 32 + 4 + 32)
+    tree = n * (9 + 5 + 8 + 13) + nn * (13 + 13 + 13 + 32 + 8)  # adjacent, counts, scan, emit; node passes
+    # leaf particles; per node: index, pre-order fields, first child, children's moments, record, parent link
+    moments = n * 32 + nn * (4 + 12 + 4 + 32 + 48 + 4)
     return dict(keys=keys, sort=sort, tree=tree, moments=moments)
 
 
