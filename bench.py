@@ -125,7 +125,10 @@ def log(*a):
 def adjoint_leg(tc, workloads, torch, dev, args):
     """fwd+adjoint ms against forward-only ms: Plummer N = 2^18, masses
     perturbed log-normally (sigma = 0.2), loss = mean |a - a*|^2 with a* the
-    field of the unperturbed masses, theta = 0.5, eps = 0.01, FP32 walk."""
+    field of the unperturbed masses, theta = 0.5, eps = 0.01, FP32 walk.  The
+    backward re-walks the tree with the forward's decisions; the variant whose
+    forward stores the interaction lists for the backward to replay is timed
+    beside it."""
     n, theta, eps = 1 << 18, 0.5, 0.01
     pos_np, _ = workloads.plummer(n, 1003, dtype=np.float32)
     m_np = workloads.lognormal_masses(n, 2003).astype(np.float32)
@@ -136,18 +139,19 @@ def adjoint_leg(tc, workloads, torch, dev, args):
     astar, _ = tree.build(pos, m_true).moments().forces(theta, eps, walk="f64")
     astar = astar.float()
 
-    def fwd():
+    def fwd(store=False):
         tree.build(pos, mass).moments()
-        a, _ = tree.forces(theta, eps, walk="f32c")
+        a, _ = tree.forces(theta, eps, walk="f32c", store_lists=store)
         return a
 
-    def fwd_adj():
-        a = fwd()
+    def fwd_adj(store=False):
+        a = fwd(store)
         g = (2.0 / n) * (a - astar)
         return tree.backward(g, None)
 
     res = {}
-    for name, fn in (("fwd", fwd), ("fwd_adj", fwd_adj)):
+    legs = (("fwd", fwd), ("fwd_adj", fwd_adj), ("fwd_adj_stored", lambda: fwd_adj(True)))
+    for name, fn in legs:
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -157,13 +161,18 @@ def adjoint_leg(tc, workloads, torch, dev, args):
         torch.cuda.synchronize()
         res[name] = (time.perf_counter() - t0) * 1e3 / args.steps
     tree.set_timing(True)
-    fwd_adj()
+    fwd_adj(False)
     st = tree.stats()
+    fwd_adj(True)
+    st_sl = tree.stats()
     tree.set_timing(False)
-    log("bench: adjoint leg N=%d: fwd %.3f ms, fwd+adjoint %.3f ms" % (n, res["fwd"], res["fwd_adj"]))
+    log("bench: adjoint leg N=%d: fwd %.3f ms, fwd+adjoint %.3f ms (with stored lists %.3f ms)" %
+        (n, res["fwd"], res["fwd_adj"], res["fwd_adj_stored"]))
     return dict(workload="plummer-N262144-lognormal-masses-theta0.5-eps0.01", n=n, walk="f32c",
                 fwd_ms=res["fwd"], fwd_adj_ms=res["fwd_adj"], ratio=res["fwd_adj"] / res["fwd"],
-                bwd_walk_ms=st["stage_ms"][6], bwd_down_ms=st["stage_ms"][7], fwd_walk_ms=st["stage_ms"][4])
+                fwd_walk_ms=st["stage_ms"][4], bwd_walk_ms=st["stage_ms"][6], bwd_down_ms=st["stage_ms"][7],
+                stored_lists=dict(fwd_adj_ms=res["fwd_adj_stored"], lists_stored=st_sl["lists_stored"],
+                                  fwd_walk_ms=st_sl["stage_ms"][4], bwd_walk_ms=st_sl["stage_ms"][6]))
 
 
 def main():

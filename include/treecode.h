@@ -55,7 +55,14 @@ typedef enum { TC_WALK_F32C = 0, TC_WALK_F64 = 1 } tc_walk;
 
 /* tc_forces flags */
 #define TC_COUNT 1u        /* record the interaction count of every target */
-#define TC_STORE_LISTS 2u  /* keep what tc_forces_backward needs to replay the walk */
+/* TC_STORE_LISTS: record, per wavefront of 64 consecutive targets in key
+ * order, every (node, accepting lanes) pair and every opened multi-particle
+ * leaf of the walk, 16 bytes each, for tc_forces_backward to replay instead of
+ * re-walking the tree.  At most 8192 records per wavefront; a wavefront whose
+ * records do not fit is re-walked by the backward pass.  The lists are kept
+ * only while they fit 4 GiB (n up to 2^21); beyond that the flag is accepted
+ * and the backward pass re-walks (same result to rounding). */
+#define TC_STORE_LISTS 2u
 
 typedef struct tc_tree tc_tree;
 
@@ -111,6 +118,9 @@ tc_status tc_forces(tc_tree* tree, double theta, double eps, double G, tc_walk m
  * Given L(acc, pot): g_acc = dL/dacc [n,3], g_pot = dL/dpot [n] (may be NULL),
  * writes g_pos = dL/dx [n,3] and g_mass = dL/dm [n] (either may be NULL), all
  * in the caller's order and in the dtype of the last walk's outputs.
+ * Each wavefront of 64 targets replays the records the last tc_forces stored
+ * (TC_STORE_LISTS) or, without them, re-walks the tree with the same
+ * decisions and arithmetic; the two agree to rounding (summation order).
  * Errors: TC_ERR_INVALID, TC_ERR_STATE (no tc_forces since the last build),
  * TC_ERR_NOMEM, TC_ERR_DEVICE. */
 tc_status tc_forces_backward(tc_tree* tree, const void* g_acc, const void* g_pot,
@@ -153,6 +163,9 @@ typedef struct {
     float stage_ms[8];       /* last timed durations: 0 keys, 1 sort, 2 tree, 3 moments,
                                 4 walk, 5 diagnostics, 6 backward walk, 7 backward down-pass
                                 (-1 if not recorded) */
+    uint32_t lists_stored;   /* 1 if the last tc_forces stored interaction lists (TC_STORE_LISTS
+                                within the list budget), else 0 */
+    uint32_t reserved;
 } tc_stats;
 
 /* Fill *out.  Synchronises `stream` when diagnostics or timings are pending.

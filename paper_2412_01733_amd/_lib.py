@@ -46,6 +46,8 @@ class TcStats(ctypes.Structure):
         ("lin_momentum", ctypes.c_double * 3),
         ("ang_momentum", ctypes.c_double * 3),
         ("stage_ms", ctypes.c_float * 8),
+        ("lists_stored", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 

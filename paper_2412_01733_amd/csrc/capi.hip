@@ -84,6 +84,7 @@ struct tc_tree {
     Buf level, first, count, next, nchild, bfs, nk0, nk1, nv0, nv1, node_sort_temp, wn, diag_temp, parent;
     // adjoint and leapfrog
     Buf node_grad, uc, part_grad, target_grad, step_temp;
+    Buf lists, list_len;       // stored interaction lists of the last tc_forces (TC_STORE_LISTS)
     uint32_t* bfs_to_pre = nullptr;  // inside nv0 or nv1
     // small device block
     Buf small;
@@ -99,6 +100,7 @@ struct tc_tree {
     uint32_t state = 0;  // bit 0 built, bit 1 moments, bit 2 forces
     tc_walk last_mode = TC_WALK_F32C;
     bool counted = false;
+    bool lists_stored = false;  // the last tc_forces stored lists that tc_forces_backward may replay
     bool diag_pending = false;
     bool build_pending = false;
     bool step_pending = false;
@@ -246,6 +248,7 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     t->diag_pending = false;
     t->build_pending = false;
     t->counted = false;
+    t->lists_stored = false;
     for (int l = 0; l < kLevels + 2; ++l) t->host->level_hist[l] = 0;
     if (n == 0) {
         Geom g{};
@@ -376,6 +379,7 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     const int64_t n = t->n;
     t->last_mode = mode;
     t->counted = (flags & TC_COUNT) != 0;
+    t->lists_stored = false;
     t->f_theta = theta;
     t->f_eps = eps;
     t->f_G = G;
@@ -399,11 +403,21 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     a.diag = P<double>(t->diag_part);
     a.status = t->status;
     a.visits = t->visits;
+    // Lists are kept only while they fit the budget; otherwise the adjoint re-walks.
+    const bool store = (flags & TC_STORE_LISTS) != 0 &&
+                       (uint64_t)waves * kListCap * sizeof(uint4) <= kListMaxBytes;
+    if (store) {
+        TC_TRY(ensure(t, t->lists, (size_t)waves * kListCap * sizeof(uint4), s));
+        TC_TRY(ensure(t, t->list_len, (size_t)waves * sizeof(uint32_t), s));
+        a.lists = P<uint4>(t->lists);
+        a.list_len = P<uint32_t>(t->list_len);
+        a.list_cap = kListCap;
+    }
 
     launch_fill_u32(t->status, 1, 0u, s);
     if (t->counted) launch_fill_u32((uint32_t*)t->visits, 4, 0u, s);
     stage_begin(t, kStWalk, s);
-    launch_walk(a, mode, t->counted, s);
+    launch_walk(a, mode, t->counted, store, s);
     stage_end(t, kStWalk, s);
     TC_TRY(check_launch("walk"));
     stage_begin(t, kStDiag, s);
@@ -419,6 +433,7 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     }
     t->diag_pending = true;
     t->state |= 4u;
+    t->lists_stored = store;
     return TC_OK;
 }
 
@@ -439,6 +454,11 @@ tc_status backward_impl(tc_tree* t, const void* g_acc, const void* g_pot, void* 
     a.node_grad = P<double>(t->node_grad);
     a.part_grad = P<double>(t->part_grad);
     a.target_grad = P<double>(t->target_grad);
+    if (t->lists_stored) {
+        a.lists = P<uint4>(t->lists);
+        a.list_len = P<uint32_t>(t->list_len);
+        a.list_cap = kListCap;
+    }
     stage_begin(t, kStBwdWalk, s);
     launch_fill_f64_zero(a.node_grad, nn * 4, s);
     launch_fill_f64_zero(a.part_grad, n * 4, s);
@@ -594,6 +614,7 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
         out->n_multi_leaves = t->n > 0 ? (int64_t)t->host->level_hist[kLevels + 1] : 0;
     }
     out->last_mode = (uint32_t)t->last_mode;
+    out->lists_stored = t->lists_stored ? 1u : 0u;
     if (t->state & 4u) {
         for (int k = 0; k < 3; ++k) out->momentum[k] = t->host->diag[k];
         out->sum_m_abs_a = t->host->diag[3];
@@ -677,7 +698,7 @@ void tc_tree_free(tc_tree* t)
                    &t->pre, &t->sorted_counts, &t->diag_part, &t->sort_temp, &t->scan_temp, &t->bounds_part,
                    &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->bfs, &t->nk0, &t->nk1,
                    &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->parent, &t->node_grad,
-                   &t->uc, &t->part_grad, &t->target_grad, &t->step_temp, &t->small};
+                   &t->uc, &t->part_grad, &t->target_grad, &t->step_temp, &t->lists, &t->list_len, &t->small};
     for (Buf* b : bufs) release(t, *b);
     for (auto& e : t->ev)
         if (e) (void)hipEventDestroy(e);

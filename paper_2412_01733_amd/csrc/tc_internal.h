@@ -132,9 +132,18 @@ struct WalkArgs {
     double* node_grad;      // [nodes, 4] breadth-first: dL/dX (3), dL/dM, accumulated
     double* part_grad;      // [n, 4] sorted order: dL/dx_j (3), dL/dm_j from opened multi-particle leaves
     double* target_grad;    // [n, 3] sorted order: dL/dx_i from the target side
+    // stored interaction lists: per wave, in visit order, records {node, kind, lane mask lo, hi};
+    // kind 0: the node was accepted by the mask's lanes; kind 1: the multi-particle leaf was
+    // opened by them.  Written by a storing forward walk, replayed by the adjoint walk.
+    uint4* lists;           // [waves, list_cap], or NULL (adjoint: re-walk)
+    uint32_t* list_len;     // [waves]: records of the wave, or kListInvalid if they did not fit
+    uint32_t list_cap;      // records per wave
 };
+constexpr uint32_t kListCap = 8192;                     // records per wave (128 KiB)
+constexpr uint32_t kListInvalid = 0xFFFFFFFFu;
+constexpr uint64_t kListMaxBytes = 4ull << 30;          // lists are stored only up to this size
 int64_t walk_waves(int64_t n);
-void launch_walk(const WalkArgs& a, tc_walk mode, bool count, hipStream_t s);
+void launch_walk(const WalkArgs& a, tc_walk mode, bool count, bool store, hipStream_t s);
 void launch_walk_adjoint(const WalkArgs& a, tc_walk mode, hipStream_t s);
 
 // adjoint.hip: top-down pass from node gradients to particle gradients.

@@ -38,11 +38,15 @@ namespace {
 
 constexpr int kWalkWaves = 4;
 constexpr int kWalkThreads = 64 * kWalkWaves;
-// Pending groups never exceed 7 per level for levels 2..20 plus 8 at the
-// deepest level (<= 141); the stack index is masked to its power-of-two size.
-constexpr int kStack = 256;
+// Pending groups never exceed 7 per level for the group levels 2..20 plus 8
+// at the deepest (<= 141); a push beyond the stack is refused and flagged.
+constexpr int kStack = 160;
 // Group partial sums are folded into the compensated totals every few groups.
 constexpr int kFlushEvery = 4;
+// Stored-list records are staged in LDS and written out this many at a time.
+constexpr uint32_t kListBuf = 32;
+// The adjoint replays stored records this many at a time.
+constexpr uint32_t kReplayChunk = 32;
 
 struct StackEntry {
     uint32_t gs, nc, mlo, mhi;
@@ -53,6 +57,13 @@ struct __align__(16) Hot32 {
     float x, y, z, m;              // FP32 offsets from the wave anchor, mass
     float tau;                     // opening threshold (s_l/theta)^2; -1 for a one-particle leaf
     uint32_t first, count, child;
+};
+
+// A replayed record with its node's data staged as for the walk.
+template <typename R>
+struct RecHot {
+    R x, y, z, m;
+    uint32_t node, kind, mlo, mhi;
 };
 
 struct __align__(16) Hot64 {
@@ -180,14 +191,18 @@ __device__ inline void add4(double* dst, double v0, double v1, double v2, double
     unsafeAtomicAdd(dst + 3, v3);
 }
 
-// ADJ = false: accelerations and potentials.  ADJ = true: the adjoint walk
-// with identical traversal and decisions (same code, same arithmetic), which
-// writes the target-side gradient per particle and accumulates the
-// source-side gradients per node (and per particle for opened
-// multi-particle leaves) with FP64 atomics after a wave reduction.
-template <bool F64, bool COUNT, bool ADJ>
+// ADJ = false: accelerations and potentials; with STORE it also records, per
+// wave and in visit order, every (node, accepting lanes) pair and every
+// multi-particle leaf opened with its lanes.  ADJ = true: the adjoint walk
+// with identical decisions and arithmetic, which writes the target-side
+// gradient per particle and accumulates the source-side gradients per node
+// (and per particle for opened multi-particle leaves) with FP64 atomics after
+// a wave reduction.  It replays the wave's stored records when there are
+// valid ones and re-walks the tree otherwise.
+template <bool F64, bool COUNT, bool ADJ, bool STORE>
 __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
 {
+    static_assert(!(ADJ && (COUNT || STORE)), "the adjoint walk neither counts nor stores");
     using R = typename std::conditional<F64, double, float>::type;
     using Hot = typename std::conditional<F64, Hot64, Hot32>::type;
     __shared__ StackEntry stk[kWalkWaves][kStack];
@@ -195,6 +210,9 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     __shared__ uint32_t stg_meta[kWalkWaves][8];
     // adjoint: per staged child, the 4 row partials of (dL/dX, dL/dM)
     __shared__ R rowp[ADJ ? kWalkWaves : 1][8][4][4];
+    __shared__ uint32_t rnode[ADJ ? kWalkWaves : 1][8];          // adjoint replay: node of each row slot
+    __shared__ uint4 lbuf[STORE ? kWalkWaves : 1][kListBuf];
+    __shared__ RecHot<R> rbuf[ADJ ? kWalkWaves : 1][ADJ ? kReplayChunk : 1];
     R tau0;
     if constexpr (F64) tau0 = a.tau0_64;
     else tau0 = a.tau0_32;
@@ -242,9 +260,172 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     uint64_t vis_nodes = 0, vis_lanes = 0;  // counting walk: wave-level node evaluations
 
     int sp = 0;
+    bool stack_over = false;
     int since_flush = 0;
+
+    // The terms of an opened leaf's particles f .. f+cnt-1 for the lanes in om,
+    // the target itself excluded.
+    auto leaf_terms = [&](const uint32_t f, const uint32_t cnt, const uint64_t om) {
+        const bool lane_open = (om >> lane) & 1ull;
+        for (uint32_t j = f; j < f + cnt; ++j) {
+            const Particle pj = a.sp[j];
+            const double xj = pj.x, yj = pj.y, zj = pj.z;
+            const R mj = (R)pj.m;
+            R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
+            if (lane_open && j != su) {
+                R ex, ey, ez;
+                if constexpr (F64) {
+                    ex = xj - xs; ey = yj - ys; ez = zj - zs;
+                } else {
+                    ex = (float)(xj - Ax) - px; ey = (float)(yj - Ay) - py; ez = (float)(zj - Az) - pz;
+                }
+                const R q = fma(ex, ex, fma(ey, ey, ez * ez)) + eps2;
+                if constexpr (!ADJ) {
+                    const R ri = rsqrt_any(q);
+                    const R mr = mj * ri;
+                    const R mr3 = mr * (ri * ri);
+                    bx = fma(mr3, ex, bx);
+                    by = fma(mr3, ey, by);
+                    bz = fma(mr3, ez, bz);
+                    bp -= mr;
+                } else {
+                    adj_term(ex, ey, ez, q, mj, Gc, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
+                    bx -= sx0;
+                    by -= sy0;
+                    bz -= sz0;
+                }
+                if constexpr (COUNT) ++nint;
+            }
+            if constexpr (ADJ) {
+                wave_sum4(sx0, sy0, sz0, sm0);
+                if (lane == 0) add4(a.part_grad + 4 * (int64_t)j, sx0, sy0, sz0, sm0);
+            }
+        }
+    };
+
+    // Adjoint: one FP64 atomic per (row slot, component) for the slots in src_m,
+    // lane = 4 k + component; node(k) names the node of slot k.
+    auto flush_sources = [&](const uint32_t src_m, auto node) {
+        if (src_m) {
+            const uint32_t k = lane >> 2, c = lane & 3;
+            if (lane < 32 && ((src_m >> k) & 1u)) {
+                const double v = (double)rowp[w][k][0][c] + (double)rowp[w][k][1][c] +
+                                 (double)rowp[w][k][2][c] + (double)rowp[w][k][3][c];
+                unsafeAtomicAdd(a.node_grad + 4 * (int64_t)node(k) + c, v);
+            }
+            wave_sync();
+        }
+    };
+
+    // Adjoint: source side of one accepted node in row slot k (sum over each
+    // 16-lane row now, over the four rows in flush_sources).
+    auto park_sources = [&](const int k, R sx0, R sy0, R sz0, R sm0) {
+        sx0 = row_sum(sx0);
+        sy0 = row_sum(sy0);
+        sz0 = row_sum(sz0);
+        sm0 = row_sum(sm0);
+        if ((lane & 15) == 0) {
+            R* rp = &rowp[w][k][lane >> 4][0];
+            rp[0] = sx0; rp[1] = sy0; rp[2] = sz0; rp[3] = sm0;
+        }
+    };
+
+    auto fold = [&]() {
+        if constexpr (F64) {
+            tx += bx; ty += by; tz += bz; tp += bp;
+        } else {
+            kahan_add(tx, cx, bx);
+            kahan_add(ty, cy, by);
+            kahan_add(tz, cz, bz);
+            kahan_add(tp, cp, bp);
+        }
+        bx = 0; by = 0; bz = 0; bp = 0;
+    };
+
+    // Storing walk: records go through a small LDS buffer to the wave's slice.
+    uint32_t nl = 0, lw = 0;
+    bool list_over = false;
+    auto list_flush = [&]() {
+        wave_sync();
+        if (lw + nl <= a.list_cap) {
+            if (lane < nl) a.lists[wave_id * (int64_t)a.list_cap + lw + lane] = lbuf[w][lane];
+        } else {
+            list_over = true;
+        }
+        lw += nl;
+        nl = 0;
+        wave_sync();
+    };
+    auto list_put = [&](const uint32_t node, const uint32_t kind, const uint64_t m) {
+        if (lane == 0) lbuf[w][nl] = make_uint4(node, kind, (uint32_t)m, (uint32_t)(m >> 32));
+        nl = uni(nl + 1);
+        if (nl == kListBuf) list_flush();
+    };
+
+    bool replayed = false;
+    if constexpr (ADJ) {
+        if (a.lists) {
+            const uint32_t len = uni(a.list_len[wave_id]);
+            if (len != kListInvalid && len <= a.list_cap) {
+                replayed = true;
+                const uint4* L = a.lists + wave_id * (int64_t)a.list_cap;
+                for (uint32_t c0 = 0; c0 < len; c0 += kReplayChunk) {
+                    // one lane per record: fetch it and stage its node as the walk does
+                    const uint32_t cn = uni(len - c0 < kReplayChunk ? len - c0 : kReplayChunk);
+                    if (lane < cn) {
+                        const uint4 rec = L[c0 + lane];
+                        const WalkNode& nd = a.nodes[rec.x];
+                        RecHot<R> e;
+                        if constexpr (F64) {
+                            e.x = nd.x; e.y = nd.y; e.z = nd.z; e.m = nd.m;
+                        } else {
+                            e.x = (float)(nd.x - Ax); e.y = (float)(nd.y - Ay); e.z = (float)(nd.z - Az);
+                            e.m = (float)nd.m;
+                        }
+                        e.node = rec.x; e.kind = rec.y; e.mlo = rec.z; e.mhi = rec.w;
+                        rbuf[w][lane] = e;
+                    }
+                    wave_sync();
+                    uint32_t src_m = 0;
+                    int nk = 0;
+                    for (uint32_t r = 0; r < cn; ++r) {
+                        const RecHot<R> e = rbuf[w][r];  // one broadcast read
+                        const uint32_t node = uni(e.node), kind = uni(e.kind);
+                        const uint64_t m = ((uint64_t)uni(e.mhi) << 32) | uni(e.mlo);
+                        if (kind == 0) {
+                            const R dx = e.x - px, dy = e.y - py, dz = e.z - pz;
+                            const R d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                            R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
+                            if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+                                adj_term(dx, dy, dz, d2 + eps2, e.m, Gc, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
+                                bx -= sx0;
+                                by -= sy0;
+                                bz -= sz0;
+                            }
+                            park_sources(nk, sx0, sy0, sz0, sm0);
+                            if (lane == 0) rnode[w][nk] = node;
+                            src_m |= 1u << nk;
+                            if (++nk == 8) {
+                                wave_sync();
+                                flush_sources(src_m, [&](uint32_t k) { return rnode[w][k]; });
+                                src_m = 0;
+                                nk = 0;
+                                fold();
+                            }
+                        } else {
+                            leaf_terms(uni(a.nodes[node].first), uni(a.nodes[node].count), m);
+                        }
+                    }
+                    wave_sync();
+                    flush_sources(src_m, [&](uint32_t k) { return rnode[w][k]; });
+                    fold();
+                }
+            }
+        }
+    }
+
     const uint64_t vmask = __ballot(valid);
-    {
+    if (!replayed) {
         const uint32_t rmeta = uni(a.nodes[0].meta);
         const uint32_t rchild = uni(a.nodes[0].child);
         if (!meta_leaf(rmeta)) {
@@ -256,7 +437,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
 
     while (sp > 0) {
         sp = uni(sp - 1);
-        const StackEntry e = stk[w][sp & (kStack - 1)];
+        const StackEntry e = stk[w][sp];
         const uint32_t gs = uni(e.gs);
         const uint32_t nc = uni(e.nc < 8u ? e.nc : 8u);
         const uint64_t mask = ((uint64_t)uni(e.mhi) << 32) | uni(e.mlo);
@@ -311,6 +492,9 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                     bp -= mr;
                     if constexpr (COUNT) ++nint;
                 }
+                if constexpr (STORE) {
+                    if (am) list_put(gs + k, 0u, am);
+                }
             } else {
                 if (am) {
                     R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
@@ -320,15 +504,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                         by -= sy0;
                         bz -= sz0;
                     }
-                    // source side: sum over each row now, over the 4 rows after the group
-                    sx0 = row_sum(sx0);
-                    sy0 = row_sum(sy0);
-                    sz0 = row_sum(sz0);
-                    sm0 = row_sum(sm0);
-                    if ((lane & 15) == 0) {
-                        R* rp = &rowp[w][k][lane >> 4][0];
-                        rp[0] = sx0; rp[1] = sy0; rp[2] = sz0; rp[3] = sm0;
-                    }
+                    park_sources(k, sx0, sy0, sz0, sm0);
                     src_m |= 1u << k;
                 }
             }
@@ -337,77 +513,36 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                 const uint32_t meta = uni(stg_meta[w][k]);
                 if (!meta_leaf(meta)) {
                     const uint32_t child = uni(h.child);
-                    if (lane == 0) stk[w][sp & (kStack - 1)] = StackEntry{child, meta_nchild(meta), (uint32_t)om, (uint32_t)(om >> 32)};
-                    sp = uni(sp + 1);
+                    if (sp < kStack) {
+                        if (lane == 0) stk[w][sp] = StackEntry{child, meta_nchild(meta), (uint32_t)om, (uint32_t)(om >> 32)};
+                        sp = uni(sp + 1);
+                    } else {
+                        stack_over = true;
+                    }
                 } else {
                     // an opened leaf: its particles one by one, the target itself excluded
-                    // (for a one-particle leaf only the lane holding that particle gets here)
+                    // (for a one-particle leaf only the lane holding that particle gets here,
+                    // and it contributes nothing)
                     const uint32_t f = uni(h.first), cnt = uni(h.count);
-                    const bool lane_open = (om >> lane) & 1ull;
-                    for (uint32_t j = f; j < f + cnt; ++j) {
-                        const Particle pj = a.sp[j];
-                        const double xj = pj.x, yj = pj.y, zj = pj.z;
-                        const R mj = (R)pj.m;
-                        R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
-                        if (lane_open && j != su) {
-                            R ex, ey, ez;
-                            if constexpr (F64) {
-                                ex = xj - xs; ey = yj - ys; ez = zj - zs;
-                            } else {
-                                ex = (float)(xj - Ax) - px; ey = (float)(yj - Ay) - py; ez = (float)(zj - Az) - pz;
-                            }
-                            const R q = fma(ex, ex, fma(ey, ey, ez * ez)) + eps2;
-                            if constexpr (!ADJ) {
-                                const R ri = rsqrt_any(q);
-                                const R mr = mj * ri;
-                                const R mr3 = mr * (ri * ri);
-                                bx = fma(mr3, ex, bx);
-                                by = fma(mr3, ey, by);
-                                bz = fma(mr3, ez, bz);
-                                bp -= mr;
-                            } else {
-                                adj_term(ex, ey, ez, q, mj, Gc, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
-                                bx -= sx0;
-                                by -= sy0;
-                                bz -= sz0;
-                            }
-                            if constexpr (COUNT) ++nint;
-                        }
-                        if constexpr (ADJ) {
-                            wave_sum4(sx0, sy0, sz0, sm0);
-                            if (lane == 0) add4(a.part_grad + 4 * (int64_t)j, sx0, sy0, sz0, sm0);
-                        }
+                    if (cnt > 1) {
+                        leaf_terms(f, cnt, om);
+                        if constexpr (STORE) list_put(gs + k, 1u, om);
                     }
                 }
             }
         }
         wave_sync();
-        if constexpr (ADJ) {
-            // one FP64 atomic per (child, component): lane = 4 k + component
-            if (src_m) {
-                const uint32_t k = lane >> 2, c = lane & 3;
-                if (lane < 32 && ((src_m >> k) & 1u)) {
-                    const double v = (double)rowp[w][k][0][c] + (double)rowp[w][k][1][c] +
-                                     (double)rowp[w][k][2][c] + (double)rowp[w][k][3][c];
-                    unsafeAtomicAdd(a.node_grad + 4 * (int64_t)(gs + k) + c, v);
-                }
-                wave_sync();
-            }
-        }
+        if constexpr (ADJ) flush_sources(src_m, [&](uint32_t k) { return gs + k; });
         if (++since_flush == kFlushEvery || sp == 0) {
             since_flush = 0;
-            if constexpr (F64) {
-                tx += bx; ty += by; tz += bz; tp += bp;
-            } else {
-                kahan_add(tx, cx, bx);
-                kahan_add(ty, cy, by);
-                kahan_add(tz, cz, bz);
-                kahan_add(tp, cp, bp);
-            }
-            bx = 0; by = 0; bz = 0; bp = 0;
+            fold();
         }
     }
-    if (sp < 0 || sp > kStack) atomicOr(a.status, 1u);
+    if (stack_over && lane == 0) atomicOr(a.status, 1u);
+    if constexpr (STORE) {
+        list_flush();
+        if (lane == 0) a.list_len[wave_id] = list_over ? kListInvalid : lw;
+    }
 
     if constexpr (ADJ) {
         if (valid) {
@@ -460,18 +595,25 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
 
 int64_t walk_waves(int64_t n) { return (n + 63) / 64; }
 
-void launch_walk(const WalkArgs& a, tc_walk mode, bool count, hipStream_t s)
+template <bool F64>
+void launch_walk_t(const WalkArgs& a, unsigned blocks, bool count, bool store, hipStream_t s)
+{
+    if (count) {
+        if (store) k_walk<F64, true, false, true><<<blocks, kWalkThreads, 0, s>>>(a);
+        else k_walk<F64, true, false, false><<<blocks, kWalkThreads, 0, s>>>(a);
+    } else {
+        if (store) k_walk<F64, false, false, true><<<blocks, kWalkThreads, 0, s>>>(a);
+        else k_walk<F64, false, false, false><<<blocks, kWalkThreads, 0, s>>>(a);
+    }
+}
+
+void launch_walk(const WalkArgs& a, tc_walk mode, bool count, bool store, hipStream_t s)
 {
     if (a.n == 0) return;
     const int64_t waves = walk_waves(a.n);
     const unsigned blocks = (unsigned)((waves + kWalkWaves - 1) / kWalkWaves);
-    if (mode == TC_WALK_F64) {
-        if (count) k_walk<true, true, false><<<blocks, kWalkThreads, 0, s>>>(a);
-        else k_walk<true, false, false><<<blocks, kWalkThreads, 0, s>>>(a);
-    } else {
-        if (count) k_walk<false, true, false><<<blocks, kWalkThreads, 0, s>>>(a);
-        else k_walk<false, false, false><<<blocks, kWalkThreads, 0, s>>>(a);
-    }
+    if (mode == TC_WALK_F64) launch_walk_t<true>(a, blocks, count, store, s);
+    else launch_walk_t<false>(a, blocks, count, store, s);
 }
 
 void launch_walk_adjoint(const WalkArgs& a, tc_walk mode, hipStream_t s)
@@ -479,8 +621,8 @@ void launch_walk_adjoint(const WalkArgs& a, tc_walk mode, hipStream_t s)
     if (a.n == 0) return;
     const int64_t waves = walk_waves(a.n);
     const unsigned blocks = (unsigned)((waves + kWalkWaves - 1) / kWalkWaves);
-    if (mode == TC_WALK_F64) k_walk<true, false, true><<<blocks, kWalkThreads, 0, s>>>(a);
-    else k_walk<false, false, true><<<blocks, kWalkThreads, 0, s>>>(a);
+    if (mode == TC_WALK_F64) k_walk<true, false, true, false><<<blocks, kWalkThreads, 0, s>>>(a);
+    else k_walk<false, false, true, false><<<blocks, kWalkThreads, 0, s>>>(a);
 }
 
 }  // namespace tc

@@ -122,7 +122,7 @@ class Tree:
                     lane_visits=int(s.lane_visits), momentum=list(s.momentum),
                     sum_m_abs_a=s.sum_m_abs_a, kinetic=s.kinetic, potential=s.potential,
                     lin_momentum=list(s.lin_momentum), ang_momentum=list(s.ang_momentum),
-                    stage_ms=list(s.stage_ms))
+                    stage_ms=list(s.stage_ms), lists_stored=bool(s.lists_stored))
 
     def export(self, moments=True):
         st = self.stats()
@@ -152,9 +152,11 @@ class Tree:
 
 
 class TreeForces(torch.autograd.Function):
-    """(acc, pot) = TreeForces.apply(pos, mass, theta, eps, G, walk).
+    """(acc, pot) = TreeForces.apply(pos, mass, theta, eps, G, walk, store_lists).
 
-    Forward: tc_build + tc_moments + tc_forces.  Backward: tc_forces_backward,
+    Forward: tc_build + tc_moments + tc_forces (storing the interaction lists
+    if store_lists and they fit the library's budget; re-walking in the
+    backward is as fast on MI355X).  Backward: tc_forces_backward,
     the adjoint of the same walk with the tree membership and every
     interaction set held fixed (the opening decisions are piecewise constant
     in x, so this is the derivative wherever no decision sits on its
@@ -162,10 +164,10 @@ class TreeForces(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, pos, mass, theta, eps, G=1.0, walk="f32c"):
+    def forward(ctx, pos, mass, theta, eps, G=1.0, walk="f32c", store_lists=False):
         tree = Tree()
         tree.build(pos.detach(), mass.detach()).moments()
-        acc, pot = tree.forces(theta, eps, G, walk=walk)
+        acc, pot = tree.forces(theta, eps, G, walk=walk, store_lists=store_lists)
         ctx.tree = tree
         ctx.in_dtype = pos.dtype
         return acc, pot
@@ -180,7 +182,7 @@ class TreeForces(torch.autograd.Function):
                                     need_mass=ctx.needs_input_grad[1])
         gpos = gpos.to(ctx.in_dtype) if gpos is not None else None
         gmass = gmass.to(ctx.in_dtype) if gmass is not None else None
-        return gpos, gmass, None, None, None, None
+        return gpos, gmass, None, None, None, None, None
 
 
 def leapfrog_step(pos, vel, mass, acc, tau, theta, eps, G=1.0, walk="f32c", pot=None, tree=None):
@@ -209,11 +211,12 @@ def leapfrog_step(pos, vel, mass, acc, tau, theta, eps, G=1.0, walk="f32c", pot=
     return t
 
 
-def forces(pos, mass, theta, eps, G=1.0, walk="f32c", count=False, tree=None):
-    """Barnes-Hut accelerations and potentials of Eq.(1): (acc, pot, tree)."""
+def forces(pos, mass, theta, eps, G=1.0, walk="f32c", count=False, tree=None, store_lists=False):
+    """Barnes-Hut accelerations and potentials of Eq.(1): (acc, pot, tree).
+    store_lists keeps the walk's interaction lists for a later tree.backward."""
     t = tree if tree is not None else Tree()
     t.build(pos, mass).moments()
-    acc, pot = t.forces(theta, eps, G, walk=walk, count=count)
+    acc, pot = t.forces(theta, eps, G, walk=walk, count=count, store_lists=store_lists)
     return acc, pot, t
 
 

@@ -37,19 +37,21 @@ def _case(n, seed, dtype=np.float64):
     return x.astype(dtype), m.astype(dtype), g, h
 
 
+@pytest.mark.parametrize("store", [False, True], ids=["rewalk", "replay"])
 @pytest.mark.parametrize("walk", ["f64", "f32c"])
 @pytest.mark.parametrize("theta", [0.0, 0.6])
-def test_backward_matches_oracle_adjoint(walk, theta):
+def test_backward_matches_oracle_adjoint(walk, theta, store):
     import paper_2412_01733_amd as tc
     n, eps = 6000, 0.01
     x, m, g, h = _case(n, 61)
-    print("adjoint case", walk, theta, flush=True)
+    print("adjoint case", walk, theta, "stored lists" if store else "re-walk", flush=True)
     T = oracle.Tree(x, m)
     L = T.lists(theta)
     gx_ref, gm_ref = T.frozen_adjoint(L, eps, g, h)
     t = tc.Tree()
     t.build(torch.from_numpy(x).to(dev()), torch.from_numpy(m).to(dev())).moments()
-    t.forces(theta, eps, walk=walk, count=True)
+    t.forces(theta, eps, walk=walk, count=True, store_lists=store)
+    assert t.stats()["lists_stored"] == store
     dt = torch.float64 if walk == "f64" else torch.float32
     gpos, gmass = t.backward(torch.from_numpy(g).to(dev(), dt), torch.from_numpy(h).to(dev(), dt))
     torch.cuda.synchronize()
@@ -61,6 +63,49 @@ def test_backward_matches_oracle_adjoint(walk, theta):
     assert np.median(ex) <= med and np.quantile(ex, 0.99) <= p99, (np.median(ex), np.quantile(ex, 0.99))
     assert np.median(em) <= med and np.quantile(em, 0.99) <= p99, (np.median(em), np.quantile(em, 0.99))
     assert same.mean() > 0.99
+
+
+@pytest.mark.parametrize("walk", ["f64", "f32c"])
+def test_replay_equals_rewalk(walk):
+    """The replay of stored lists and the re-walk evaluate the same terms; only
+    the grouping of the target-side sums differs."""
+    import paper_2412_01733_amd as tc
+    n, eps, theta = 6000, 0.01, 0.6
+    x, m, g, h = _case(n, 71)
+    t = tc.Tree()
+    t.build(torch.from_numpy(x).to(dev()), torch.from_numpy(m).to(dev())).moments()
+    dt = torch.float64 if walk == "f64" else torch.float32
+    ga, gp = torch.from_numpy(g).to(dev(), dt), torch.from_numpy(h).to(dev(), dt)
+    out = {}
+    for store in (False, True):
+        t.forces(theta, eps, walk=walk, store_lists=store)
+        gpos, gmass = t.backward(ga, gp)
+        torch.cuda.synchronize()
+        out[store] = (gpos.double().cpu().numpy(), gmass.double().cpu().numpy())
+    bar = 1e-12 if walk == "f64" else 1e-5
+    ex = rel(out[True][0], out[False][0])
+    em = np.abs(out[True][1] - out[False][1]) / np.abs(out[False][1])
+    assert np.quantile(ex, 0.99) <= bar and np.quantile(em, 0.99) <= bar, (np.quantile(ex, 0.99), np.quantile(em, 0.99))
+
+
+def test_list_overflow_falls_back_to_rewalk():
+    """theta = 0: every wave accepts the one-particle leaf of each particle outside
+    its 64 targets, so each wave needs >= n - 64 > 8192 records: every wave's list
+    overflows, is marked invalid, and the backward pass re-walks it."""
+    import paper_2412_01733_amd as tc
+    n, eps, theta = 12000, 0.01, 0.0
+    x, m, g, h = _case(n, 81)
+    T = oracle.Tree(x, m)
+    gx_ref, gm_ref = T.frozen_adjoint(T.lists(theta), eps, g, h)
+    t = tc.Tree()
+    t.build(torch.from_numpy(x).to(dev()), torch.from_numpy(m).to(dev())).moments()
+    t.forces(theta, eps, walk="f64", store_lists=True)
+    assert t.stats()["lists_stored"]
+    gpos, gmass = t.backward(torch.from_numpy(g).to(dev()), torch.from_numpy(h).to(dev()))
+    torch.cuda.synchronize()
+    ex = rel(gpos.cpu().numpy(), gx_ref)
+    em = np.abs(gmass.cpu().numpy() - gm_ref) / np.abs(gm_ref)
+    assert np.quantile(ex, 0.99) <= 1e-10 and np.quantile(em, 0.99) <= 1e-10, (np.quantile(ex, 0.99), np.quantile(em, 0.99))
 
 
 def test_treeforces_gradcheck_fp64():
