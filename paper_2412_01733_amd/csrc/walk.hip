@@ -118,20 +118,20 @@ __device__ inline R wave_sum(R v)
 // T = q^-3/2 I - 3 q^-5/2 Delta Delta^T the source receives
 //   dL/dy  = G mu (T g + q^-3/2 Delta h)   (the target receives the negative),
 //   dL/dmu = G (Delta.g q^-3/2 - h q^-1/2).
+// Both are linear in (g, h): the caller passes G g and G h.
 template <typename R>
-__device__ inline void adj_term(R dx, R dy, R dz, R q, R mu, R G, R gx, R gy, R gz, R h, R& sx, R& sy, R& sz,
-                                R& sm)
+__device__ inline void adj_term(R dx, R dy, R dz, R q, R mu, R gx, R gy, R gz, R h, R& sx, R& sy, R& sz, R& sm)
 {
     const R ri = rsqrt_any(q);
     const R ri2 = ri * ri;
     const R ri3 = ri2 * ri;
     const R dg = fma(dx, gx, fma(dy, gy, dz * gz));
-    const R c1 = G * mu * ri3;
+    const R c1 = mu * ri3;
     const R c2 = c1 * fma((R)-3 * ri2, dg, h);
     sx = fma(c1, gx, c2 * dx);
     sy = fma(c1, gy, c2 * dy);
     sz = fma(c1, gz, c2 * dz);
-    sm = G * fma(dg, ri3, -h * ri);
+    sm = fma(dg, ri3, -h * ri);
 }
 
 // Sum over the wave of four values; the result is uniform.
@@ -209,8 +209,12 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     __shared__ Hot stg[kWalkWaves][8];
     __shared__ uint32_t stg_meta[kWalkWaves][8];
     // adjoint: per staged child, the 4 row partials of (dL/dX, dL/dM)
-    __shared__ R rowp[ADJ ? kWalkWaves : 1][8][4][4];
-    __shared__ uint32_t rnode[ADJ ? kWalkWaves : 1][8];          // adjoint replay: node of each row slot
+    // adjoint, source side: FP64 walk - per pending node, the 4 row partials of
+    // (dL/dX, dL/dM); FP32 walk - per pending node, every lane's 4 values
+    constexpr int kSrcBatch = F64 ? 8 : 2;
+    __shared__ R rowp[(ADJ && F64) ? kWalkWaves : 1][8][4][4];
+    __shared__ float sval[(ADJ && !F64) ? kWalkWaves : 1][2][4][64];
+    __shared__ uint32_t rnode[ADJ ? kWalkWaves : 1][8];          // node of each pending slot
     __shared__ uint4 lbuf[STORE ? kWalkWaves : 1][kListBuf];
     __shared__ RecHot<R> rbuf[ADJ ? kWalkWaves : 1][ADJ ? kReplayChunk : 1];
     R tau0;
@@ -240,15 +244,15 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     }
     const R eps2 = (R)a.eps2;
     const R Gc = (R)a.G;
-    R gxl = 0, gyl = 0, gzl = 0, hl = 0;  // adjoint: dL/da and dL/dphi of this lane's target
+    R gxl = 0, gyl = 0, gzl = 0, hl = 0;  // adjoint: G dL/da and G dL/dphi of this lane's target
     if constexpr (ADJ) {
         if (valid) {
             const uint32_t i = a.perm[s];
             const R* ga = (const R*)a.g_acc;
-            gxl = ga[3 * (int64_t)i + 0];
-            gyl = ga[3 * (int64_t)i + 1];
-            gzl = ga[3 * (int64_t)i + 2];
-            if (a.g_pot) hl = ((const R*)a.g_pot)[i];
+            gxl = Gc * ga[3 * (int64_t)i + 0];
+            gyl = Gc * ga[3 * (int64_t)i + 1];
+            gzl = Gc * ga[3 * (int64_t)i + 2];
+            if (a.g_pot) hl = Gc * ((const R*)a.g_pot)[i];
         }
     }
 
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                     bz = fma(mr3, ez, bz);
                     bp -= mr;
                 } else {
-                    adj_term(ex, ey, ez, q, mj, Gc, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
+                    adj_term(ex, ey, ez, q, mj, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
                     bx -= sx0;
                     by -= sy0;
                     bz -= sz0;
@@ -303,31 +307,54 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
         }
     };
 
-    // Adjoint: one FP64 atomic per (row slot, component) for the slots in src_m,
-    // lane = 4 k + component; node(k) names the node of slot k.
-    auto flush_sources = [&](const uint32_t src_m, auto node) {
-        if (src_m) {
+    // Adjoint, source side.  The per-lane values of up to kSrcBatch accepted
+    // nodes wait in LDS; a flush reduces each (node, component) over the wave
+    // in a fixed order and adds it to node_grad with one FP64 atomic.
+    int nsrc = 0;
+    auto src_flush = [&]() {
+        if (nsrc == 0) return;
+        wave_sync();
+        if constexpr (F64) {
+            // lane = 4 k + component; the four 16-lane row partials added in FP64
             const uint32_t k = lane >> 2, c = lane & 3;
-            if (lane < 32 && ((src_m >> k) & 1u)) {
+            if (k < (uint32_t)nsrc) {
                 const double v = (double)rowp[w][k][0][c] + (double)rowp[w][k][1][c] +
                                  (double)rowp[w][k][2][c] + (double)rowp[w][k][3][c];
-                unsafeAtomicAdd(a.node_grad + 4 * (int64_t)node(k) + c, v);
+                unsafeAtomicAdd(a.node_grad + 4 * (int64_t)rnode[w][k] + c, v);
             }
-            wave_sync();
+        } else {
+            // lane = 32 k + 8 component + eighth: 8 values each, then the eighths
+            // (quad swaps and the half-row mirror sum each aligned group of 8 lanes)
+            const uint32_t k = lane >> 5, c = (lane >> 3) & 3, e8 = lane & 7;
+            const float4* v4 = reinterpret_cast<const float4*>(&sval[w][k][c][8 * e8]);
+            const float4 v0 = v4[0], v1 = v4[1];
+            float t = ((v0.x + v0.y) + (v0.z + v0.w)) + ((v1.x + v1.y) + (v1.z + v1.w));
+            t += dpp_f(t, 0);
+            t += dpp_f(t, 1);
+            t += dpp_f(t, 2);
+            if (e8 == 0 && k < (uint32_t)nsrc) unsafeAtomicAdd(a.node_grad + 4 * (int64_t)rnode[w][k] + c, (double)t);
         }
+        wave_sync();
+        nsrc = 0;
     };
-
-    // Adjoint: source side of one accepted node in row slot k (sum over each
-    // 16-lane row now, over the four rows in flush_sources).
-    auto park_sources = [&](const int k, R sx0, R sy0, R sz0, R sm0) {
-        sx0 = row_sum(sx0);
-        sy0 = row_sum(sy0);
-        sz0 = row_sum(sz0);
-        sm0 = row_sum(sm0);
-        if ((lane & 15) == 0) {
-            R* rp = &rowp[w][k][lane >> 4][0];
-            rp[0] = sx0; rp[1] = sy0; rp[2] = sz0; rp[3] = sm0;
+    auto src_put = [&](const uint32_t node, R sx0, R sy0, R sz0, R sm0) {
+        if constexpr (F64) {
+            sx0 = row_sum(sx0);
+            sy0 = row_sum(sy0);
+            sz0 = row_sum(sz0);
+            sm0 = row_sum(sm0);
+            if ((lane & 15) == 0) {
+                R* rp = &rowp[w][nsrc][lane >> 4][0];
+                rp[0] = sx0; rp[1] = sy0; rp[2] = sz0; rp[3] = sm0;
+            }
+        } else {
+            sval[w][nsrc][0][lane] = sx0;
+            sval[w][nsrc][1][lane] = sy0;
+            sval[w][nsrc][2][lane] = sz0;
+            sval[w][nsrc][3][lane] = sm0;
         }
+        if (lane == 0) rnode[w][nsrc] = node;
+        if (++nsrc == kSrcBatch) src_flush();
     };
 
     auto fold = [&]() {
@@ -386,8 +413,6 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                         rbuf[w][lane] = e;
                     }
                     wave_sync();
-                    uint32_t src_m = 0;
-                    int nk = 0;
                     for (uint32_t r = 0; r < cn; ++r) {
                         const RecHot<R> e = rbuf[w][r];  // one broadcast read
                         const uint32_t node = uni(e.node), kind = uni(e.kind);
@@ -397,29 +422,20 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                             const R d2 = fma(dx, dx, fma(dy, dy, dz * dz));
                             R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
                             if (__builtin_amdgcn_inverse_ballot_w64(m)) {
-                                adj_term(dx, dy, dz, d2 + eps2, e.m, Gc, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
+                                adj_term(dx, dy, dz, d2 + eps2, e.m, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
                                 bx -= sx0;
                                 by -= sy0;
                                 bz -= sz0;
                             }
-                            park_sources(nk, sx0, sy0, sz0, sm0);
-                            if (lane == 0) rnode[w][nk] = node;
-                            src_m |= 1u << nk;
-                            if (++nk == 8) {
-                                wave_sync();
-                                flush_sources(src_m, [&](uint32_t k) { return rnode[w][k]; });
-                                src_m = 0;
-                                nk = 0;
-                                fold();
-                            }
+                            src_put(node, sx0, sy0, sz0, sm0);
                         } else {
                             leaf_terms(uni(a.nodes[node].first), uni(a.nodes[node].count), m);
                         }
                     }
-                    wave_sync();
-                    flush_sources(src_m, [&](uint32_t k) { return rnode[w][k]; });
+                    wave_sync();  // the next chunk overwrites rbuf
                     fold();
                 }
+                src_flush();
             }
         }
     }
@@ -469,7 +485,6 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
             vis_nodes += nc;
             vis_lanes += (uint64_t)nc * (uint64_t)__popcll(mask);
         }
-        uint32_t src_m = 0;  // adjoint: children with at least one accepting lane
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             if ((uint32_t)k >= nc) break;
@@ -499,13 +514,12 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
                 if (am) {
                     R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
                     if (__builtin_amdgcn_inverse_ballot_w64(am)) {
-                        adj_term(dx, dy, dz, d2 + eps2, h.m, Gc, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
+                        adj_term(dx, dy, dz, d2 + eps2, h.m, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
                         bx -= sx0;
                         by -= sy0;
                         bz -= sz0;
                     }
-                    park_sources(k, sx0, sy0, sz0, sm0);
-                    src_m |= 1u << k;
+                    src_put(gs + k, sx0, sy0, sz0, sm0);
                 }
             }
             const uint64_t om = mask & ~am;
@@ -532,13 +546,13 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
             }
         }
         wave_sync();
-        if constexpr (ADJ) flush_sources(src_m, [&](uint32_t k) { return gs + k; });
         if (++since_flush == kFlushEvery || sp == 0) {
             since_flush = 0;
             fold();
         }
     }
     if (stack_over && lane == 0) atomicOr(a.status, 1u);
+    if constexpr (ADJ) src_flush();
     if constexpr (STORE) {
         list_flush();
         if (lane == 0) a.list_len[wave_id] = list_over ? kListInvalid : lw;

@@ -42,15 +42,15 @@ def _case(n, seed, dtype=np.float64):
 @pytest.mark.parametrize("theta", [0.0, 0.6])
 def test_backward_matches_oracle_adjoint(walk, theta, store):
     import paper_2412_01733_amd as tc
-    n, eps = 6000, 0.01
+    n, eps, G = 6000, 0.01, 1.3
     x, m, g, h = _case(n, 61)
     print("adjoint case", walk, theta, "stored lists" if store else "re-walk", flush=True)
     T = oracle.Tree(x, m)
     L = T.lists(theta)
-    gx_ref, gm_ref = T.frozen_adjoint(L, eps, g, h)
+    gx_ref, gm_ref = T.frozen_adjoint(L, eps, g, h, G)
     t = tc.Tree()
     t.build(torch.from_numpy(x).to(dev()), torch.from_numpy(m).to(dev())).moments()
-    t.forces(theta, eps, walk=walk, count=True, store_lists=store)
+    t.forces(theta, eps, G, walk=walk, count=True, store_lists=store)
     assert t.stats()["lists_stored"] == store
     dt = torch.float64 if walk == "f64" else torch.float32
     gpos, gmass = t.backward(torch.from_numpy(g).to(dev(), dt), torch.from_numpy(h).to(dev(), dt))
