@@ -58,6 +58,8 @@ __host__ __device__ inline uint32_t meta_nchild(uint32_t m) { return m & 0xFu; }
 __host__ __device__ inline uint32_t meta_level(uint32_t m) { return (m >> 8) & 0x1Fu; }
 __host__ __device__ inline bool meta_leaf(uint32_t m) { return (m >> 16) & 1u; }
 __host__ __device__ inline bool meta_single(uint32_t m) { return (m >> 17) & 1u; }
+// level + 32 * single (bit 13 repeats the single flag): the walk's threshold table index
+__host__ __device__ inline uint32_t meta_tau_index(uint32_t m) { return (m >> 8) & 0x3Fu; }
 
 // ---------------------------------------------------------------------------
 // launch wrappers (each defined next to its kernels)

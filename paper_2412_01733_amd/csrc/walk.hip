@@ -55,8 +55,8 @@ struct StackEntry {
 // What a child needs on the hot path, staged once per group in LDS.
 struct __align__(16) Hot32 {
     float x, y, z, m;              // FP32 offsets from the wave anchor, mass
-    float tau;                     // opening threshold (s_l/theta)^2; -1 for a one-particle leaf
     uint32_t first, count, child;
+    float tau;                     // opening threshold (s_l/theta)^2; -1 for a one-particle leaf
 };
 
 // A replayed record with its node's data staged as for the walk.
@@ -207,6 +207,8 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     using Hot = typename std::conditional<F64, Hot64, Hot32>::type;
     __shared__ StackEntry stk[kWalkWaves][kStack];
     __shared__ Hot stg[kWalkWaves][8];
+    // opening thresholds by meta_tau_index: tau0 4^-l for level l, -1 for a one-particle leaf
+    __shared__ R taut[kWalkWaves][64];
     __shared__ uint32_t stg_meta[kWalkWaves][8];
     // adjoint: per staged child, the 4 row partials of (dL/dX, dL/dM)
     // adjoint, source side: FP64 walk - per pending node, the 4 row partials of
@@ -226,6 +228,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
     const int64_t wave_id = (int64_t)blockIdx.x * kWalkWaves + w;
     const int64_t base = wave_id * 64;
     if (base >= a.n) return;  // whole wave; no block barrier follows
+    taut[w][lane] = lane < 32 ? (R)ldexp(tau0, -2 * (int)lane) : (R)-1;  // exact power-of-two scaling
     const int64_t s = base + lane;
     const bool valid = s < a.n;
     const int64_t sl = valid ? s : base;
@@ -455,7 +458,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
         sp = uni(sp - 1);
         const StackEntry e = stk[w][sp];
         const uint32_t gs = uni(e.gs);
-        const uint32_t nc = uni(e.nc < 8u ? e.nc : 8u);
+        const uint32_t nc = min(uni(e.nc), 8u);
         const uint64_t mask = ((uint64_t)uni(e.mhi) << 32) | uni(e.mlo);
         bool ovl = false;  // may the child contain one of this wave's targets?
         const WalkNode* grp = a.nodes + gs;  // uniform base of the group
@@ -463,15 +466,13 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
             const WalkNode nd = grp[lane];
             ovl = nd.first < wave_end && nd.first + nd.count > (uint32_t)base;
             Hot h;
-            const bool single = meta_single(nd.meta);
             if constexpr (F64) {
                 h.x = nd.x; h.y = nd.y; h.z = nd.z; h.m = nd.m;
             } else {
                 h.x = (float)(nd.x - Ax); h.y = (float)(nd.y - Ay); h.z = (float)(nd.z - Az);
                 h.m = (float)nd.m;
             }
-            // (s_l/theta)^2 = tau0 4^-l: an exact power-of-two scaling
-            h.tau = single ? (R)-1 : (R)ldexp(tau0, -2 * (int)meta_level(nd.meta));
+            h.tau = taut[w][meta_tau_index(nd.meta)];
             h.first = nd.first;
             h.count = nd.count;
             h.child = nd.child;
