@@ -64,18 +64,14 @@ def walk_traffic_bytes():
 PEAK_HBM_GBPS = 8000.0               # MI355X HBM3E
 
 
-def stage_bytes(n, nn, singles, p=4):
+def stage_bytes(n, nn, p=4):
     """Compulsory HBM bytes of each build stage: what its kernels read and
-    write once (no re-reads), for n particles, nn nodes of which `singles`
-    are one-particle leaves, and p-byte inputs."""
+    write once (no re-reads), for n particles, nn nodes and p-byte inputs."""
     keys = n * (4 * p + (4 * p + 8 + 4 + 4 * p))            # bounds; keys + index + packed record
     sort = n * (8 * (8 + 24) + (4 + 4 * p + 32))             # 8 radix passes (count + move); gather
-    # per particle: adjacent levels, node counts, scan, owner map; per node: owner, emit, child
-    # counts, level keys, one radix pass, breadth-first records; one-particle leaves' records
-    tree = n * (9 + 5 + 8 + 5) + nn * (34 + 13 + 13 + 32 + 37) + singles * 64
-    # every record's tail read, children's moments read once, parent links; the other nodes'
-    # record writes and indices
-    moments = nn * (16 + 32 + 4) + (nn - singles) * (32 + 16 + 8)
+    tree = n * (9 + 5 + 8 + 13) + nn * (13 + 13 + 13 + 32 + 8)  # adjacent, counts, scan, emit; node passes
+    # leaf particles; per node: index, pre-order fields, first child, children's moments, record, parent link
+    moments = n * 32 + nn * (4 + 12 + 4 + 32 + 48 + 4)
     return dict(keys=keys, sort=sort, tree=tree, moments=moments)
 
 
@@ -320,7 +316,7 @@ def main():
 
     head = walks[0]
     r = res[head]
-    sb = stage_bytes(n, r["n_nodes"], r["util"]["leaves"] - r["util"]["multi_leaves"])
+    sb = stage_bytes(n, r["n_nodes"])
     hbm = {}
     for k, b in sb.items():
         ms = r["stage_ms"][k]

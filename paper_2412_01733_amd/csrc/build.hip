@@ -120,37 +120,25 @@ __device__ inline int64_t cell_end(const uint64_t* __restrict__ k, int64_t n, in
     return lo;
 }
 
-// Owner of every pre-order node: the particle it starts at.
-__global__ __launch_bounds__(256) void k_owner(const int8_t* __restrict__ c, const uint32_t* __restrict__ pre,
-                                               int64_t n, uint32_t* __restrict__ owner)
+__global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ k, const int8_t* __restrict__ c,
+                                              const uint32_t* __restrict__ pre, int64_t n,
+                                              uint8_t* __restrict__ level, uint32_t* __restrict__ first,
+                                              uint32_t* __restrict__ count, uint32_t* __restrict__ next)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int lo, hi;
     node_range(c, s, lo, hi);
+    const int cs = (int)c[s];
+    const uint64_t key = k[s];
     uint32_t p = pre[s];
-    for (int l = lo; l <= hi; ++l, ++p) owner[p] = (uint32_t)s;
-}
-
-// One thread per node (so one search per thread: the particles that start
-// many nested cells do not serialise their searches).
-__global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ k, const int8_t* __restrict__ c,
-                                              const uint32_t* __restrict__ pre, const uint32_t* __restrict__ owner,
-                                              int64_t n, int64_t nn, uint8_t* __restrict__ level,
-                                              uint32_t* __restrict__ first, uint32_t* __restrict__ count,
-                                              uint32_t* __restrict__ next)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nn) return;
-    const int64_t s = owner[p];
-    int lo, hi;
-    node_range(c, s, lo, hi);
-    const int l = lo + (int)(p - (int64_t)pre[s]);
-    const int64_t end = (l > (int)c[s]) ? s + 1 : cell_end(k, n, s, k[s], l);
-    level[p] = (uint8_t)l;
-    first[p] = (uint32_t)s;
-    count[p] = (uint32_t)(end - s);
-    next[p] = pre[end];
+    for (int l = lo; l <= hi; ++l, ++p) {
+        int64_t end = (l > cs) ? s + 1 : cell_end(k, n, s, key, l);
+        level[p] = (uint8_t)l;
+        first[p] = (uint32_t)s;
+        count[p] = (uint32_t)(end - s);
+        next[p] = pre[end];
+    }
 }
 
 __device__ inline bool is_internal(uint8_t level, uint32_t count) { return count >= 2 && level < kMaxLevel; }
@@ -185,34 +173,12 @@ __global__ __launch_bounds__(256) void k_level_keys(const uint8_t* __restrict__ 
     vals[p] = (uint32_t)p;
 }
 
-// Inverse permutation, and the breadth-first walk records as far as the
-// topology fixes them: first, count and meta of every node (the first child
-// is filled in by the upward pass), and the whole record of a one-particle
-// leaf, whose moments are its particle verbatim.  That takes two thirds of
-// the nodes out of the level-by-level upward pass.
-__global__ __launch_bounds__(256) void k_bfs_records(const uint32_t* __restrict__ bfs_to_pre, int64_t nn,
-                                                     const uint8_t* __restrict__ level,
-                                                     const uint32_t* __restrict__ first,
-                                                     const uint32_t* __restrict__ count,
-                                                     const uint32_t* __restrict__ nchild,
-                                                     const Particle* __restrict__ sp, uint32_t* __restrict__ bfs,
-                                                     WalkNode* __restrict__ wn)
+__global__ __launch_bounds__(256) void k_bfs_scatter(const uint32_t* __restrict__ bfs_to_pre, int64_t nn,
+                                                     uint32_t* __restrict__ bfs)
 {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nn) return;
-    const uint32_t p = bfs_to_pre[b];
-    bfs[p] = (uint32_t)b;
-    const uint32_t f = first[p], c = count[p], nc = nchild[p], l = level[p];
-    const bool single = nc == 0 && c == 1;
-    const uint32_t meta = nc | (l << 8) | (single ? (1u << 13) : 0u) | (nc == 0 ? (1u << 16) : 0u) |
-                          (single ? (1u << 17) : 0u);
-    uint4* o = reinterpret_cast<uint4*>(wn + b);
-    if (single) {
-        const Particle q = sp[f];
-        o[0] = make_uint4(__double2loint(q.x), __double2hiint(q.x), __double2loint(q.y), __double2hiint(q.y));
-        o[1] = make_uint4(__double2loint(q.z), __double2hiint(q.z), __double2loint(q.m), __double2hiint(q.m));
-    }
-    o[2] = make_uint4(f, c, 0u, meta);
+    bfs[bfs_to_pre[b]] = (uint32_t)b;
 }
 
 }  // namespace
@@ -231,13 +197,11 @@ void launch_node_counts(const int8_t* c, int64_t n, uint32_t* cnt, uint32_t* lev
     k_node_counts<<<b, 256, 0, s>>>(c, n, cnt, level_hist);
 }
 
-void launch_emit_nodes(const uint64_t* skeys, const int8_t* c, const uint32_t* pre, int64_t n, int64_t nn,
-                       uint32_t* owner, uint8_t* level, uint32_t* first, uint32_t* count, uint32_t* next,
-                       hipStream_t s)
+void launch_emit_nodes(const uint64_t* skeys, const int8_t* c, const uint32_t* pre, int64_t n,
+                       uint8_t* level, uint32_t* first, uint32_t* count, uint32_t* next, hipStream_t s)
 {
     if (n == 0) return;
-    k_owner<<<grid_for(n, 256), 256, 0, s>>>(c, pre, n, owner);
-    k_emit<<<grid_for(nn, 256), 256, 0, s>>>(skeys, c, pre, owner, n, nn, level, first, count, next);
+    k_emit<<<grid_for(n, 256), 256, 0, s>>>(skeys, c, pre, n, level, first, count, next);
 }
 
 void launch_count_children(const uint8_t* level, const uint32_t* count, const uint32_t* next, int64_t nn,
@@ -247,15 +211,14 @@ void launch_count_children(const uint8_t* level, const uint32_t* count, const ui
     k_count_children<<<grid_for(nn, 256), 256, 0, s>>>(level, count, next, nn, nchild);
 }
 
-void launch_bfs_order(const uint8_t* level, const uint32_t* first, const uint32_t* count, const uint32_t* nchild,
-                      const Particle* sp, int64_t nn, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
-                      void* sort_temp, uint32_t* bfs, uint32_t** bfs_to_pre, WalkNode* wn, hipStream_t s)
+void launch_bfs_order(const uint8_t* level, int64_t nn, uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                      void* sort_temp, uint32_t* bfs, uint32_t** bfs_to_pre, hipStream_t s)
 {
     if (nn == 0) return;
     k_level_keys<<<grid_for(nn, 256), 256, 0, s>>>(level, nn, k0, v0);
     uint64_t* ko;
     radix_sort_pairs(k0, v0, k1, v1, nn, 8, sort_temp, s, &ko, bfs_to_pre);
-    k_bfs_records<<<grid_for(nn, 256), 256, 0, s>>>(*bfs_to_pre, nn, level, first, count, nchild, sp, bfs, wn);
+    k_bfs_scatter<<<grid_for(nn, 256), 256, 0, s>>>(*bfs_to_pre, nn, bfs);
 }
 
 }  // namespace tc

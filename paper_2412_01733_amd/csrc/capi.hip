@@ -327,15 +327,12 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     TC_TRY(ensure(t, t->wn, (size_t)nn * sizeof(WalkNode), s));
     TC_TRY(ensure(t, t->parent, m4, s));
 
-    // nchild doubles as the owner scratch: it is written only after the emit
-    launch_emit_nodes(t->skeys, P<int8_t>(t->c), P<uint32_t>(t->pre), n, nn, P<uint32_t>(t->nchild),
-                      P<uint8_t>(t->level), P<uint32_t>(t->first), P<uint32_t>(t->count), P<uint32_t>(t->next), s);
+    launch_emit_nodes(t->skeys, P<int8_t>(t->c), P<uint32_t>(t->pre), n, P<uint8_t>(t->level), P<uint32_t>(t->first),
+                      P<uint32_t>(t->count), P<uint32_t>(t->next), s);
     launch_count_children(P<uint8_t>(t->level), P<uint32_t>(t->count), P<uint32_t>(t->next), nn,
                           P<uint32_t>(t->nchild), s);
-    launch_bfs_order(P<uint8_t>(t->level), P<uint32_t>(t->first), P<uint32_t>(t->count), P<uint32_t>(t->nchild),
-                     P<Particle>(t->sp), nn, P<uint64_t>(t->nk0), P<uint32_t>(t->nv0), P<uint64_t>(t->nk1),
-                     P<uint32_t>(t->nv1), t->node_sort_temp.p, P<uint32_t>(t->bfs), &t->bfs_to_pre,
-                     P<WalkNode>(t->wn), s);
+    launch_bfs_order(P<uint8_t>(t->level), nn, P<uint64_t>(t->nk0), P<uint32_t>(t->nv0), P<uint64_t>(t->nk1),
+                     P<uint32_t>(t->nv1), t->node_sort_temp.p, P<uint32_t>(t->bfs), &t->bfs_to_pre, s);
     stage_end(t, kStTree, s);
     TC_TRY(check_launch("tree"));
     t->state = 1;
@@ -346,8 +343,9 @@ tc_status moments_impl(tc_tree* t, hipStream_t s)
 {
     if (t->n > 0) {
         stage_begin(t, kStMoments, s);
-        launch_moments(t->host->level_off, t->bfs_to_pre, P<uint32_t>(t->bfs), t->skeys, P<Particle>(t->sp),
-                       t->geom, P<WalkNode>(t->wn), P<uint32_t>(t->parent), s);
+        launch_moments(t->host->level_off, t->bfs_to_pre, P<uint32_t>(t->bfs), P<uint32_t>(t->first),
+                       P<uint32_t>(t->count), P<uint32_t>(t->nchild), t->skeys, P<Particle>(t->sp), t->geom,
+                       P<WalkNode>(t->wn), P<uint32_t>(t->parent), s);
         stage_end(t, kStMoments, s);
         TC_TRY(check_launch("moments"));
     }

@@ -11,8 +11,7 @@
 //   leaf of one particle:  M = m_j, X = x_j exactly;
 //   otherwise:             M = sum M_c, X = (sum M_c X_c) / M,
 //                          X = the cell centre when M = 0.
-// The tree build has written every record's first, count and meta and the
-// whole record of every one-particle leaf; this pass completes the rest.
+// The same pass writes the node's whole walk record.
 #include "tc_internal.h"
 
 namespace tc {
@@ -39,31 +38,45 @@ __device__ inline void cell_centre(uint64_t key, int level, const Geom* g, doubl
     }
 }
 
-// One node at breadth-first position b whose record the tree build has
-// started (first, count, meta); one-particle leaves are already complete.
+// One node, at breadth-first position b (pre-order index p).
 __device__ inline void moments_node(int64_t b, int l, const uint32_t* __restrict__ bfs_to_pre,
-                                    const uint32_t* __restrict__ bfs, const uint64_t* __restrict__ skeys,
-                                    const Particle* __restrict__ sp, const Geom* __restrict__ g,
-                                    WalkNode* __restrict__ wn, uint32_t* __restrict__ parent)
+                                    const uint32_t* __restrict__ bfs, const uint32_t* __restrict__ first,
+                                    const uint32_t* __restrict__ count, const uint32_t* __restrict__ nchild,
+                                    const uint64_t* __restrict__ skeys, const Particle* __restrict__ sp,
+                                    const Geom* __restrict__ g, WalkNode* __restrict__ wn,
+                                    uint32_t* __restrict__ parent)
 {
-    uint4* o = reinterpret_cast<uint4*>(wn + b);
-    const uint4 tail = o[2];
-    const uint32_t f = tail.x, c = tail.y, meta = tail.w, nc = meta_nchild(meta);
-    if (meta_single(meta)) return;
+    const uint32_t p = bfs_to_pre[b];
+    const uint32_t f = first[p], c = count[p], nc = nchild[p];
     double M = 0.0, X[3];
     bool centre = false;
     uint32_t child = 0;
-    double S0 = 0.0, S1 = 0.0, S2 = 0.0;
     if (nc == 0) {
-        for (uint32_t j = f; j < f + c; ++j) {
-            const Particle q = sp[j];
-            M += q.m;
-            S0 += q.m * q.x;
-            S1 += q.m * q.y;
-            S2 += q.m * q.z;
+        if (c == 1) {
+            const Particle q = sp[f];
+            M = q.m;
+            X[0] = q.x;
+            X[1] = q.y;
+            X[2] = q.z;
+        } else {
+            double S0 = 0.0, S1 = 0.0, S2 = 0.0;
+            for (uint32_t j = f; j < f + c; ++j) {
+                const Particle q = sp[j];
+                M += q.m;
+                S0 += q.m * q.x;
+                S1 += q.m * q.y;
+                S2 += q.m * q.z;
+            }
+            if (M == 0.0) centre = true;
+            else {
+                X[0] = S0 / M;
+                X[1] = S1 / M;
+                X[2] = S2 / M;
+            }
         }
     } else {
-        child = bfs[bfs_to_pre[b] + 1];  // the first child follows its parent in pre-order
+        child = bfs[p + 1];  // the first child follows its parent in pre-order
+        double S0 = 0.0, S1 = 0.0, S2 = 0.0;
         for (uint32_t k = 0; k < nc; ++k) {
             parent[child + k] = (uint32_t)b;
             const double2 xy = *reinterpret_cast<const double2*>(&wn[child + k].x);
@@ -74,24 +87,29 @@ __device__ inline void moments_node(int64_t b, int l, const uint32_t* __restrict
             S1 += mc * xy.y;
             S2 += mc * zm.x;
         }
-    }
-    if (M == 0.0) centre = true;
-    else {
-        X[0] = S0 / M;
-        X[1] = S1 / M;
-        X[2] = S2 / M;
+        if (M == 0.0) centre = true;
+        else {
+            X[0] = S0 / M;
+            X[1] = S1 / M;
+            X[2] = S2 / M;
+        }
     }
     if (centre) cell_centre(skeys[f], l, g, X);
+    const bool single = nc == 0 && c == 1;
+    const uint32_t meta = nc | ((uint32_t)l << 8) | (single ? (1u << 13) : 0u) | (nc == 0 ? (1u << 16) : 0u) |
+                          (single ? (1u << 17) : 0u);
+    uint4* o = reinterpret_cast<uint4*>(wn + b);
     o[0] = make_uint4(__double2loint(X[0]), __double2hiint(X[0]), __double2loint(X[1]), __double2hiint(X[1]));
     o[1] = make_uint4(__double2loint(X[2]), __double2hiint(X[2]), __double2loint(M), __double2hiint(M));
-    if (nc) o[2] = make_uint4(f, c, child, meta);
+    o[2] = make_uint4(f, c, child, meta);
 }
 
-#define MOM_ARGS                                                                                        \
-    const uint32_t *__restrict__ bfs_to_pre, const uint32_t *__restrict__ bfs, const uint64_t *__restrict__ skeys, \
-        const Particle *__restrict__ sp, const Geom *__restrict__ g, WalkNode *__restrict__ wn,        \
+#define MOM_ARGS                                                                                                  \
+    const uint32_t *__restrict__ bfs_to_pre, const uint32_t *__restrict__ bfs, const uint32_t *__restrict__ first, \
+        const uint32_t *__restrict__ count, const uint32_t *__restrict__ nchild, const uint64_t *__restrict__ skeys, \
+        const Particle *__restrict__ sp, const Geom *__restrict__ g, WalkNode *__restrict__ wn,                  \
         uint32_t *__restrict__ parent
-#define MOM_PASS bfs_to_pre, bfs, skeys, sp, g, wn, parent
+#define MOM_PASS bfs_to_pre, bfs, first, count, nchild, skeys, sp, g, wn, parent
 
 // One level with many nodes: one thread per node.
 __global__ __launch_bounds__(256) void k_moments_level(int l, uint32_t b0, uint32_t b1, MOM_ARGS)
@@ -132,8 +150,8 @@ __global__ __launch_bounds__(256) void k_export_moments(const WalkNode* __restri
 }  // namespace
 
 void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
-                    const uint64_t* skeys, const Particle* sp, const Geom* g, WalkNode* wn, uint32_t* parent,
-                    hipStream_t s)
+                    const uint32_t* first, const uint32_t* count, const uint32_t* nchild, const uint64_t* skeys,
+                    const Particle* sp, const Geom* g, WalkNode* wn, uint32_t* parent, hipStream_t s)
 {
     LevelOffsets off;
     for (int l = 0; l <= kLevels; ++l) off.off[l] = level_off_host[l];
