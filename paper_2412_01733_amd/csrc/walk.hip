@@ -199,8 +199,11 @@ __device__ inline void add4(double* dst, double v0, double v1, double v2, double
 // (and per particle for opened multi-particle leaves) with FP64 atomics after
 // a wave reduction.  It replays the wave's stored records when there are
 // valid ones and re-walks the tree otherwise.
+// The walk is bound by latency at full occupancy, so the timed forward walks
+// are held to 64 VGPRs (8 waves per SIMD); the FP64 one needs the request.
 template <bool F64, bool COUNT, bool ADJ, bool STORE>
-__global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs a)
+__global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu((F64 && !COUNT && !ADJ && !STORE) ? 8 : 1)))
+void k_walk(WalkArgs a)
 {
     static_assert(!(ADJ && (COUNT || STORE)), "the adjoint walk neither counts nor stores");
     using R = typename std::conditional<F64, double, float>::type;
