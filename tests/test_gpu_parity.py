@@ -231,3 +231,61 @@ def test_tree_reuse_grows_and_shrinks():
         torch.cuda.synchronize()
         a, ph, _ = oracle.forces(pos, m, 0.5, 0.01)
         check_forces(dict(acc=acc.cpu().double().numpy(), pot=pot.cpu().double().numpy()), a, ph, "f32c")
+
+
+def test_allocation_failure_is_reported_cleanly():
+    """An allocator that fails after k successful allocations: every call
+    reports TC_ERR_NOMEM (or succeeds), nothing is launched on a missing
+    buffer, the handle can be freed, and the default allocator works after."""
+    import ctypes
+    import paper_2412_01733_amd as tc
+    from paper_2412_01733_amd import _lib as m
+    L = m.load()
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    pos, mass = workloads.plummer(20000, 5, dtype=np.float32)
+    p = torch.from_numpy(pos).to(dev())
+    mm = torch.from_numpy(mass).to(dev())
+    acc = torch.empty((20000, 3), dtype=torch.float32, device=dev())
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    outcomes = []
+    try:
+        for k in (0, 1, 2, 4, 8, 16, 64):
+            count = [0]
+
+            def alloc(nbytes, s, ctx, count=count, k=k):
+                if count[0] >= k:
+                    return None
+                count[0] += 1
+                ptr = ctypes.c_void_p()
+                return ptr.value if hip.hipMalloc(ctypes.byref(ptr), nbytes) == 0 else None
+
+            def free(ptr, s, ctx):
+                torch.cuda.synchronize()
+                hip.hipFree(ptr)
+
+            fa, ff = m.ALLOC_FN(alloc), m.FREE_FN(free)
+            assert L.tc_set_allocator(fa, ff, None) == m.TC_OK
+            h = ctypes.c_void_p()
+            st = L.tc_build(ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(mm.data_ptr()), 20000, m.TC_F32, stream,
+                            ctypes.byref(h))
+            if st == m.TC_OK:
+                st = L.tc_moments(h, stream)
+            if st == m.TC_OK:
+                st = L.tc_forces(h, 0.5, 0.01, 1.0, 0, 0, ctypes.c_void_p(acc.data_ptr()), None, stream)
+            torch.cuda.synchronize()
+            assert st in (m.TC_OK, m.TC_ERR_NOMEM), (k, st)
+            if st == m.TC_ERR_NOMEM:
+                assert b"allocation" in L.tc_last_error()
+            outcomes.append(st)
+            if h.value:
+                L.tc_tree_free(h)
+            torch.cuda.synchronize()
+    finally:
+        assert L.tc_set_allocator(m.ALLOC_FN(), m.FREE_FN(), None) == m.TC_OK
+    assert outcomes[0] == m.TC_ERR_NOMEM and outcomes[-1] == m.TC_OK, outcomes
+    a, _, _ = tc.forces(p, mm, 0.5, 0.01)
+    ref, _, _ = oracle.forces(pos, mass, 0.5, 0.01)
+    e = rel_err(a.cpu().double().numpy(), ref)
+    assert np.median(e) <= 1e-5
