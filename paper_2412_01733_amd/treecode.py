@@ -109,8 +109,10 @@ class Tree:
     def set_timing(self, on=True):
         """Record per-stage HIP-event durations (applied at the next build if no handle yet)."""
         self._timing = bool(on)
+        self._timing_applied = False
         if self._h.value:
             check(self._lib.tc_tree_set_timing(self._h, 1 if on else 0))
+            self._timing_applied = True
 
     def stats(self):
         s = _lib.TcStats()
