@@ -198,8 +198,8 @@ def main():
 
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the TreeCode path here is a single-GPU build "
-              "(see DESIGN.md for how it would shard); --gpus %d is not supported" % args.gpus,
-              file=sys.stderr)
+              "(targets would shard by contiguous key ranges over a replicated tree); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
