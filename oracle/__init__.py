@@ -24,12 +24,17 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "treecode_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The mutation tests point this at a copy of the oracle built with one
+# planted mistake, to show that the pins catch it; it is never rebuilt.
+_LIB_OVERRIDE = os.environ.get("TREECODE_ORACLE_LIB")
 
 CFLAGS = ["-O3", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-pthread"]
 
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc into oracle/liboracle.so."""
+    if _LIB_OVERRIDE:
+        return _LIB_OVERRIDE
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
@@ -43,8 +48,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(build())
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         D = ctypes.c_double
