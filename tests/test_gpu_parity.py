@@ -87,6 +87,10 @@ CASES = [
     ("plummer16k_f64", lambda: workloads.plummer(16384, 1000), 0.7, 0.01),
     ("plummer5000_f32", lambda: workloads.plummer(5000, 3, dtype=np.float32), 0.5, 0.01),
     ("dups4097_f64", lambda: (_dups(4097, 4), np.full(4097, 1.0 / 4097)), 0.6, 0.001),
+    # the paper's own theta = 1 on its workload class (disc + halo), and theta = 1.2: above
+    # 1/sqrt(3) the rule that a node holding the target is never accepted decides many terms
+    ("disc20k_f32_theta1", lambda: workloads.disc_galaxy(16000, 4000, 5, dtype=np.float32)[0::2], 1.0, 0.02),
+    ("plummer8k_f64_theta1.2", lambda: workloads.plummer(8192, 6), 1.2, 0.01),
 ]
 
 
