@@ -11,7 +11,10 @@ times (one tc_build + tc_moments + tc_forces through the C ABI).
     0.1% of targets, F32C on under 1% (distances within FP32 rounding of the
     opening threshold);
   * momentum ratio |sum m a| / sum m |a| over all N: the F32C walk within
-    1e-6 (absolute) of the F64 walk, which matches the oracle per target.
+    1e-6 (absolute) of the F64 walk, which matches the oracle per target;
+  * Newton's shell theorem over the whole F32C field (theta = 0.5): shell means
+    of the radial acceleration for 0.1 < r < 5 against -G M(<r) / r^2 to 0.2%,
+    a pin independent of the oracle.
 """
 import numpy as np
 import pytest
@@ -77,3 +80,36 @@ def test_fullsize_sampled_forces(big, theta):
         assert np.mean(cnt != rn) <= flip_bar, (walk, np.mean(cnt != rn))
         rp_ratio[walk] = np.linalg.norm(st["momentum"]) / st["sum_m_abs_a"]
     assert abs(rp_ratio["f32c"] - rp_ratio["f64"]) <= 1e-6, rp_ratio
+
+
+def test_fullsize_plummer_radial_profile(big):
+    """Newton's shell theorem for the whole 1e7 field of the F32C walk: the
+    mean radial acceleration over shells 0.1 < r < 5 (20 equal-count bins)
+    equals -G M(<r) / r^2, with M(<r) the enclosed mass of the drawn sample
+    (its Poisson noise removed) to 0.2%, and the truncated-Plummer closed
+    form to that plus 4 sigma of the sample's Poisson noise in M(<r)."""
+    tree, pos, m = big["tree"], big["pos"].astype(np.float64), big["m"].astype(np.float64)
+    acc, _ = tree.forces(0.5, EPS, walk="f32c")
+    a = acc.double().cpu().numpy()
+    r = np.linalg.norm(pos, axis=1)
+    ar = (a * pos).sum(1) / r
+    o = np.argsort(r)
+    m_emp = np.empty_like(r)
+    m_emp[o] = np.concatenate([[0.0], np.cumsum(m[o])[:-1]])
+    inner = (r > 0.1) & (r < 5.0)
+    edges = np.quantile(r[inner], np.linspace(0, 1, 21))
+    worst_emp = worst_cf = 0.0
+    for lo_, hi_ in zip(edges[:-1], edges[1:]):
+        sel = (r >= lo_) & (r < hi_)
+        got = ar[sel].mean()
+        want_emp = -(m_emp[sel] / r[sel] ** 2).mean()
+        f = workloads.plummer_enclosed(r[sel])
+        want_cf = -(f / r[sel] ** 2).mean()
+        fm = float(np.median(f))
+        sigma = np.sqrt(fm * (1.0 - fm) / N) / fm  # relative Poisson noise of M(<r)
+        e_emp, e_cf = abs(got / want_emp - 1.0), abs(got / want_cf - 1.0)
+        print("shell %.3f-%.3f: vs drawn %.2e, vs closed form %.2e (sigma %.1e)" % (lo_, hi_, e_emp, e_cf, sigma), flush=True)
+        assert e_emp < 2e-3, (lo_, hi_, e_emp)
+        assert e_cf < 2e-3 + 4 * sigma, (lo_, hi_, e_cf, sigma)
+        worst_emp, worst_cf = max(worst_emp, e_emp), max(worst_cf, e_cf)
+    print("worst: vs drawn %.2e, vs closed form %.2e" % (worst_emp, worst_cf), flush=True)
