@@ -94,8 +94,10 @@ tc_status tc_build(const void* pos, const void* mass, int64_t n, tc_dtype dtype,
 /* Upward pass: total mass M and centre of mass X of every node (monopole,
  * TreeCode description of section 2).  One-particle leaf: M = m, X = x
  * verbatim; otherwise M = sum M_c, X = sum(M_c X_c) / M in FP64 with the
- * children in octant order; M = 0 gives X = the cell centre.
- * Errors: TC_ERR_INVALID (null tree), TC_ERR_STATE (no successful tc_build). */
+ * children in octant order; M = 0 gives X = the cell centre.  Also lays out
+ * the walk's target order (see tc_tree_target_order).
+ * Errors: TC_ERR_INVALID (null tree), TC_ERR_STATE (no successful tc_build),
+ * TC_ERR_NOMEM. */
 tc_status tc_moments(tc_tree* tree, void* stream);
 
 /* Accelerations and potentials, Eq.(1), by the Barnes-Hut walk.  For target
@@ -160,7 +162,8 @@ typedef struct {
     double potential;        /*   sum m phi / 2 (0 if pot was NULL) */
     double lin_momentum[3];  /*   sum m v */
     double ang_momentum[3];  /*   sum m x cross v */
-    float stage_ms[8];       /* last timed durations: 0 keys, 1 sort, 2 tree, 3 moments,
+    float stage_ms[8];       /* last timed durations: 0 keys, 1 sort, 2 tree, 3 moments (with the
+                                walk's target order),
                                 4 walk, 5 diagnostics, 6 backward walk, 7 backward down-pass
                                 (-1 if not recorded) */
     uint32_t lists_stored;   /* 1 if the last tc_forces stored interaction lists (TC_STORE_LISTS
@@ -185,6 +188,14 @@ tc_status tc_tree_set_timing(tc_tree* tree, int on);
 tc_status tc_tree_export(const tc_tree* tree, uint64_t* keys, uint32_t* perm, uint8_t* level,
                          uint32_t* first, uint32_t* count, double* com, double* mass,
                          void* stream);
+
+/* The walk's target order, set by tc_moments: order u32[n] (device), the
+ * sorted positions of the particles along the Hilbert curve; wavefront w of
+ * every walk serves the targets order[64 w .. 64 w + 63].  It fixes only how
+ * targets are grouped, never a result (each target's interaction set is its
+ * own, section 2).  Provided for tests and diagnostics.
+ * Errors: TC_ERR_INVALID, TC_ERR_STATE (no tc_moments since the last build). */
+tc_status tc_tree_target_order(const tc_tree* tree, uint32_t* order, void* stream);
 
 /* Per-target interaction counts of the last tc_forces run with TC_COUNT, in
  * the caller's order: counts u32[n] (device).

@@ -21,7 +21,7 @@ TC_COUNT, TC_STORE_LISTS = 1, 2
 # Every exported symbol of the C ABI, as declared in include/treecode.h.
 EXPORTS = ("tc_set_allocator", "tc_build", "tc_moments", "tc_forces", "tc_forces_backward",
            "tc_leapfrog_step", "tc_tree_stats", "tc_tree_set_timing", "tc_tree_export",
-           "tc_interaction_counts", "tc_tree_free", "tc_last_error", "tc_version")
+           "tc_interaction_counts", "tc_tree_target_order", "tc_tree_free", "tc_last_error", "tc_version")
 
 
 class TcStats(ctypes.Structure):
@@ -94,6 +94,8 @@ def load():
     L.tc_tree_export.restype = st
     L.tc_interaction_counts.argtypes = [P, P, P]
     L.tc_interaction_counts.restype = st
+    L.tc_tree_target_order.argtypes = [P, P, P]
+    L.tc_tree_target_order.restype = st
     L.tc_tree_free.argtypes = [P]
     L.tc_tree_free.restype = None
     L.tc_last_error.argtypes = []

@@ -82,6 +82,7 @@ struct tc_tree {
     Buf sort_temp, scan_temp, bounds_part;
     // node-sized
     Buf level, first, count, next, nchild, bfs, nk0, nk1, nv0, nv1, node_sort_temp, wn, diag_temp, parent;
+    Buf nord, order;           // the walk's target order (particle-sized) and its node-sized scratch
     // adjoint and leapfrog
     Buf node_grad, uc, part_grad, target_grad, step_temp;
     Buf lists, list_len;       // stored interaction lists of the last tc_forces (TC_STORE_LISTS)
@@ -346,6 +347,9 @@ tc_status moments_impl(tc_tree* t, hipStream_t s)
         launch_moments(t->host->level_off, t->bfs_to_pre, P<uint32_t>(t->bfs), P<uint32_t>(t->first),
                        P<uint32_t>(t->count), P<uint32_t>(t->nchild), t->skeys, P<Particle>(t->sp), t->geom,
                        P<WalkNode>(t->wn), P<uint32_t>(t->parent), s);
+        TC_TRY(ensure(t, t->nord, (size_t)t->nn * sizeof(uint2), s));
+        TC_TRY(ensure(t, t->order, (size_t)t->n * 4, s));
+        launch_target_order(t->host->level_off, P<WalkNode>(t->wn), P<uint2>(t->nord), P<uint32_t>(t->order), s);
         stage_end(t, kStMoments, s);
         TC_TRY(check_launch("moments"));
     }
@@ -359,6 +363,7 @@ tc_status walk_args(tc_tree* t, double theta, double eps, double G, tc_walk mode
 {
     a.nodes = P<WalkNode>(t->wn);
     a.sp = P<Particle>(t->sp);
+    a.order = P<uint32_t>(t->order);
     a.perm = t->perm;
     a.n = t->n;
     a.eps2 = eps * eps;
@@ -680,6 +685,17 @@ tc_status tc_tree_export(const tc_tree* t, uint64_t* keys, uint32_t* perm, uint8
     return TC_OK;
 }
 
+tc_status tc_tree_target_order(const tc_tree* t, uint32_t* order, void* stream)
+{
+    g_err.clear();
+    if (!t || !order) return fail(TC_ERR_INVALID, "tc_tree_target_order: NULL argument");
+    if (!(t->state & 2u)) return fail(TC_ERR_STATE, "tc_tree_target_order: no tc_moments since the last build");
+    TC_TRY(check_device(t));
+    if (t->n == 0) return TC_OK;
+    HIP_TRY(hipMemcpyAsync(order, t->order.p, (size_t)t->n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return TC_OK;
+}
+
 tc_status tc_interaction_counts(const tc_tree* t, uint32_t* counts, void* stream)
 {
     g_err.clear();
@@ -697,7 +713,7 @@ void tc_tree_free(tc_tree* t)
     Buf* bufs[] = {&t->keys0, &t->keys1, &t->vals0, &t->vals1, &t->rec, &t->sp, &t->c, &t->cnt,
                    &t->pre, &t->sorted_counts, &t->diag_part, &t->sort_temp, &t->scan_temp, &t->bounds_part,
                    &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->bfs, &t->nk0, &t->nk1,
-                   &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->parent, &t->node_grad,
+                   &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->parent, &t->nord, &t->order, &t->node_grad,
                    &t->uc, &t->part_grad, &t->target_grad, &t->step_temp, &t->lists, &t->list_len, &t->small};
     for (Buf* b : bufs) release(t, *b);
     for (auto& e : t->ev)

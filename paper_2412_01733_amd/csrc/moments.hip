@@ -96,8 +96,9 @@ __device__ inline void moments_node(int64_t b, int l, const uint32_t* __restrict
     }
     if (centre) cell_centre(skeys[f], l, g, X);
     const bool single = nc == 0 && c == 1;
+    const uint32_t octant = l > 0 ? (uint32_t)(skeys[f] >> (3 * (kMaxLevel - l))) & 7u : 0u;
     const uint32_t meta = nc | ((uint32_t)l << 8) | (single ? (1u << 13) : 0u) | (nc == 0 ? (1u << 16) : 0u) |
-                          (single ? (1u << 17) : 0u);
+                          (single ? (1u << 17) : 0u) | (octant << 18);
     uint4* o = reinterpret_cast<uint4*>(wn + b);
     o[0] = make_uint4(__double2loint(X[0]), __double2hiint(X[0]), __double2loint(X[1]), __double2hiint(X[1]));
     o[1] = make_uint4(__double2loint(X[2]), __double2hiint(X[2]), __double2loint(M), __double2hiint(M));

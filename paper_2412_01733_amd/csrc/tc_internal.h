@@ -34,7 +34,8 @@ struct __align__(16) WalkNode {
     uint32_t first;   // sorted index of the first particle
     uint32_t count;   // particles in the node
     uint32_t child;   // group index of the first child (internal nodes)
-    uint32_t meta;    // bits 0-3 nchild, bits 8-12 level, bit 16 leaf, bit 17 one-particle leaf
+    uint32_t meta;    // bits 0-3 nchild, bits 8-12 level, bit 16 leaf, bit 17 one-particle leaf,
+                      // bits 18-20 the node's octant in its parent (key digit at its level)
 };
 static_assert(sizeof(WalkNode) == 48, "WalkNode layout");
 
@@ -58,6 +59,7 @@ __host__ __device__ inline uint32_t meta_nchild(uint32_t m) { return m & 0xFu; }
 __host__ __device__ inline uint32_t meta_level(uint32_t m) { return (m >> 8) & 0x1Fu; }
 __host__ __device__ inline bool meta_leaf(uint32_t m) { return (m >> 16) & 1u; }
 __host__ __device__ inline bool meta_single(uint32_t m) { return (m >> 17) & 1u; }
+__host__ __device__ inline uint32_t meta_octant(uint32_t m) { return (m >> 18) & 7u; }
 // level + 32 * single (bit 13 repeats the single flag): the walk's threshold table index
 __host__ __device__ inline uint32_t meta_tau_index(uint32_t m) { return (m >> 8) & 0x3Fu; }
 
@@ -116,6 +118,7 @@ void launch_export_moments(const WalkNode* wn, const uint32_t* bfs, int64_t nn, 
 struct WalkArgs {
     const WalkNode* nodes;
     const Particle* sp;     // particles in key order
+    const uint32_t* order;  // [n] targets by wavefront: wavefront w takes order[64 w .. 64 w + 63]
     const uint32_t* perm;
     int64_t n;
     double eps2;
@@ -147,6 +150,11 @@ constexpr uint64_t kListMaxBytes = 4ull << 30;          // lists are stored only
 int64_t walk_waves(int64_t n);
 void launch_walk(const WalkArgs& a, tc_walk mode, bool count, bool store, hipStream_t s);
 void launch_walk_adjoint(const WalkArgs& a, tc_walk mode, hipStream_t s);
+
+// order.hip: the walk's target order (Hilbert order of the particles), from
+// the finished breadth-first records top-down; nord is node-sized scratch.
+void launch_target_order(const uint32_t* level_off_host, const WalkNode* wn, uint2* nord, uint32_t* order,
+                         hipStream_t s);
 
 // adjoint.hip: top-down pass from node gradients to particle gradients.
 void launch_adjoint_down(const uint32_t* level_off_host, const WalkNode* wn, const uint32_t* parent,

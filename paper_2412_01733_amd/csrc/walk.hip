@@ -226,21 +226,31 @@ void k_walk(WalkArgs a)
     if constexpr (F64) tau0 = a.tau0_64;
     else tau0 = a.tau0_32;
 
-    const int w = threadIdx.x >> 6;
+    // FP64 walk: the wave index made uniform keeps the per-wave LDS slices in
+    // scalar registers, so the kernel fits 64 VGPRs (8 waves per SIMD) unspilled
+    const int w = F64 ? uni((int)(threadIdx.x >> 6)) : (int)(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
     const int64_t wave_id = (int64_t)blockIdx.x * kWalkWaves + w;
     const int64_t base = wave_id * 64;
     if (base >= a.n) return;  // whole wave; no block barrier follows
     taut[w][lane] = lane < 32 ? (R)ldexp(tau0, -2 * (int)lane) : (R)-1;  // exact power-of-two scaling
-    const int64_t s = base + lane;
-    const bool valid = s < a.n;
-    const int64_t sl = valid ? s : base;
-    const uint32_t su = (uint32_t)s;
-    const uint32_t wave_end = (uint32_t)(base + 64 < a.n ? base + 64 : a.n);
+    // this lane's target (sorted position) and the range of sorted positions the
+    // wavefront's targets span (a superset of them: only a node overlapping it
+    // can hold one of the targets)
+    const bool valid = base + lane < a.n;
+    const uint32_t first_t = uni(a.order[base]);
+    const uint32_t su = valid ? a.order[base + lane] : first_t;
+    uint32_t smin = valid ? su : 0xFFFFFFFFu, smax = valid ? su : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        smin = min(smin, (uint32_t)__shfl_xor((int)smin, o, 64));
+        smax = max(smax, (uint32_t)__shfl_xor((int)smax, o, 64));
+    }
+    const uint32_t wave_lo = uni(smin), wave_end = uni(smax) + 1u;
 
-    const Particle anchor = a.sp[base];
+    const Particle anchor = a.sp[first_t];
     const double Ax = anchor.x, Ay = anchor.y, Az = anchor.z;
-    const Particle self = a.sp[sl];
+    const Particle self = a.sp[su];
     const double xs = self.x, ys = self.y, zs = self.z;
     R px, py, pz;
     if constexpr (F64) {
@@ -253,7 +263,7 @@ void k_walk(WalkArgs a)
     R gxl = 0, gyl = 0, gzl = 0, hl = 0;  // adjoint: G dL/da and G dL/dphi of this lane's target
     if constexpr (ADJ) {
         if (valid) {
-            const uint32_t i = a.perm[s];
+            const uint32_t i = a.perm[su];
             const R* ga = (const R*)a.g_acc;
             gxl = Gc * ga[3 * (int64_t)i + 0];
             gyl = Gc * ga[3 * (int64_t)i + 1];
@@ -467,7 +477,7 @@ void k_walk(WalkArgs a)
         const WalkNode* grp = a.nodes + gs;  // uniform base of the group
         if (lane < nc) {
             const WalkNode nd = grp[lane];
-            ovl = nd.first < wave_end && nd.first + nd.count > (uint32_t)base;
+            ovl = nd.first < wave_end && nd.first + nd.count > wave_lo;
             Hot h;
             if constexpr (F64) {
                 h.x = nd.x; h.y = nd.y; h.z = nd.z; h.m = nd.m;
@@ -564,7 +574,7 @@ void k_walk(WalkArgs a)
 
     if constexpr (ADJ) {
         if (valid) {
-            double* tg = a.target_grad + 3 * s;
+            double* tg = a.target_grad + 3 * (int64_t)su;
             if constexpr (F64) {
                 tg[0] = tx; tg[1] = ty; tg[2] = tz;
             } else {
@@ -583,13 +593,13 @@ void k_walk(WalkArgs a)
 
     double dm[4] = {0.0, 0.0, 0.0, 0.0};
     if (valid) {
-        const uint32_t i = a.perm[s];
+        const uint32_t i = a.perm[su];
         R* acc = (R*)a.acc;
         acc[3 * (int64_t)i + 0] = ox;
         acc[3 * (int64_t)i + 1] = oy;
         acc[3 * (int64_t)i + 2] = oz;
         if (a.pot) ((R*)a.pot)[i] = op;
-        if constexpr (COUNT) a.counts[s] = nint;
+        if constexpr (COUNT) a.counts[su] = nint;
         const double m = self.m;
         const double ex = (double)ox, ey = (double)oy, ez = (double)oz;
         dm[0] = m * ex;

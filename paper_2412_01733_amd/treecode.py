@@ -146,6 +146,13 @@ class Tree:
                                            _ptr(out.get("mass")), _stream_ptr(dev)))
         return out
 
+    def target_order(self):
+        """Sorted positions of the particles in the walk's target order (Hilbert order)."""
+        o = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            check(self._lib.tc_tree_target_order(self._h, _ptr(o), _stream_ptr(self.device)))
+        return o
+
     def interaction_counts(self):
         c = torch.empty(self.n, dtype=torch.int32, device=self.device)
         with torch.cuda.device(self.device):
