@@ -82,7 +82,7 @@ struct tc_tree {
     Buf sort_temp, scan_temp, bounds_part;
     // node-sized
     Buf level, first, count, next, nchild, bfs, nk0, nk1, nv0, nv1, node_sort_temp, wn, diag_temp, parent;
-    Buf nord, order;           // the walk's target order (particle-sized) and its node-sized scratch
+    Buf topo, nord, order;     // the walk's target order (particle-sized); dense topology and scratch (node-sized)
     // adjoint and leapfrog
     Buf node_grad, uc, part_grad, target_grad, step_temp;
     Buf lists, list_len;       // stored interaction lists of the last tc_forces (TC_STORE_LISTS)
@@ -327,6 +327,7 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     TC_TRY(ensure(t, t->node_sort_temp, radix_temp_bytes(nn), s));
     TC_TRY(ensure(t, t->wn, (size_t)nn * sizeof(WalkNode), s));
     TC_TRY(ensure(t, t->parent, m4, s));
+    TC_TRY(ensure(t, t->topo, (size_t)nn * 16, s));
 
     launch_emit_nodes(t->skeys, P<int8_t>(t->c), P<uint32_t>(t->pre), n, P<uint8_t>(t->level), P<uint32_t>(t->first),
                       P<uint32_t>(t->count), P<uint32_t>(t->next), s);
@@ -346,10 +347,10 @@ tc_status moments_impl(tc_tree* t, hipStream_t s)
         stage_begin(t, kStMoments, s);
         launch_moments(t->host->level_off, t->bfs_to_pre, P<uint32_t>(t->bfs), P<uint32_t>(t->first),
                        P<uint32_t>(t->count), P<uint32_t>(t->nchild), t->skeys, P<Particle>(t->sp), t->geom,
-                       P<WalkNode>(t->wn), P<uint32_t>(t->parent), s);
+                       P<WalkNode>(t->wn), P<uint32_t>(t->parent), P<uint4>(t->topo), s);
         TC_TRY(ensure(t, t->nord, (size_t)t->nn * sizeof(uint2), s));
         TC_TRY(ensure(t, t->order, (size_t)t->n * 4, s));
-        launch_target_order(t->host->level_off, P<WalkNode>(t->wn), P<uint2>(t->nord), P<uint32_t>(t->order), s);
+        launch_target_order(t->host->level_off, P<uint4>(t->topo), P<uint2>(t->nord), P<uint32_t>(t->order), s);
         stage_end(t, kStMoments, s);
         TC_TRY(check_launch("moments"));
     }
@@ -713,7 +714,7 @@ void tc_tree_free(tc_tree* t)
     Buf* bufs[] = {&t->keys0, &t->keys1, &t->vals0, &t->vals1, &t->rec, &t->sp, &t->c, &t->cnt,
                    &t->pre, &t->sorted_counts, &t->diag_part, &t->sort_temp, &t->scan_temp, &t->bounds_part,
                    &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->bfs, &t->nk0, &t->nk1,
-                   &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->parent, &t->nord, &t->order, &t->node_grad,
+                   &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->parent, &t->topo, &t->nord, &t->order, &t->node_grad,
                    &t->uc, &t->part_grad, &t->target_grad, &t->step_temp, &t->lists, &t->list_len, &t->small};
     for (Buf* b : bufs) release(t, *b);
     for (auto& e : t->ev)

@@ -44,7 +44,7 @@ __device__ inline void moments_node(int64_t b, int l, const uint32_t* __restrict
                                     const uint32_t* __restrict__ count, const uint32_t* __restrict__ nchild,
                                     const uint64_t* __restrict__ skeys, const Particle* __restrict__ sp,
                                     const Geom* __restrict__ g, WalkNode* __restrict__ wn,
-                                    uint32_t* __restrict__ parent)
+                                    uint32_t* __restrict__ parent, uint4* __restrict__ topo)
 {
     const uint32_t p = bfs_to_pre[b];
     const uint32_t f = first[p], c = count[p], nc = nchild[p];
@@ -103,14 +103,15 @@ __device__ inline void moments_node(int64_t b, int l, const uint32_t* __restrict
     o[0] = make_uint4(__double2loint(X[0]), __double2hiint(X[0]), __double2loint(X[1]), __double2hiint(X[1]));
     o[1] = make_uint4(__double2loint(X[2]), __double2hiint(X[2]), __double2loint(M), __double2hiint(M));
     o[2] = make_uint4(f, c, child, meta);
+    topo[b] = make_uint4(f, c, child, meta);  // the same topology half, densely, for the target-order pass
 }
 
 #define MOM_ARGS                                                                                                  \
     const uint32_t *__restrict__ bfs_to_pre, const uint32_t *__restrict__ bfs, const uint32_t *__restrict__ first, \
         const uint32_t *__restrict__ count, const uint32_t *__restrict__ nchild, const uint64_t *__restrict__ skeys, \
         const Particle *__restrict__ sp, const Geom *__restrict__ g, WalkNode *__restrict__ wn,                  \
-        uint32_t *__restrict__ parent
-#define MOM_PASS bfs_to_pre, bfs, first, count, nchild, skeys, sp, g, wn, parent
+        uint32_t *__restrict__ parent, uint4 *__restrict__ topo
+#define MOM_PASS bfs_to_pre, bfs, first, count, nchild, skeys, sp, g, wn, parent, topo
 
 // One level with many nodes: one thread per node.
 __global__ __launch_bounds__(256) void k_moments_level(int l, uint32_t b0, uint32_t b1, MOM_ARGS)
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(256) void k_export_moments(const WalkNode* __restri
 
 void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
                     const uint32_t* first, const uint32_t* count, const uint32_t* nchild, const uint64_t* skeys,
-                    const Particle* sp, const Geom* g, WalkNode* wn, uint32_t* parent, hipStream_t s)
+                    const Particle* sp, const Geom* g, WalkNode* wn, uint32_t* parent, uint4* topo, hipStream_t s)
 {
     LevelOffsets off;
     for (int l = 0; l <= kLevels; ++l) off.off[l] = level_off_host[l];

@@ -9,7 +9,8 @@
 // interaction set and terms are its own.
 //
 // Every octree cell is a contiguous range of the Hilbert order, just as it is
-// of the key order, so the order follows from the tree top-down: a node's
+// of the key order, so the order follows from the tree top-down (reading the
+// dense breadth-first topology records {first, count, child, meta}): a node's
 // particles start at its offset; its children follow each other in the order
 // of their Hilbert digits at their level (siblings share all higher digits);
 // a leaf lays out its particles in key order.  Level by level, root first
@@ -77,10 +78,10 @@ __device__ inline uint32_t hilbert_step(uint32_t st, uint32_t d, uint32_t* child
 // order; an internal node gives each child its offset and Hilbert state.
 // nord[b] = {offset, state} was written by the parent (the root starts at
 // offset 0 in the root state).
-__device__ inline void order_node(int64_t b, const WalkNode* __restrict__ wn, uint2* __restrict__ nord,
+__device__ inline void order_node(int64_t b, const uint4* __restrict__ topo, uint2* __restrict__ nord,
                                   uint32_t* __restrict__ order)
 {
-    const uint4 rec = reinterpret_cast<const uint4*>(wn + b)[2];  // first, count, child, meta
+    const uint4 rec = topo[b];  // first, count, child, meta
     const uint2 me = b == 0 ? make_uint2(0u, kRootState) : nord[b];
     if (meta_leaf(rec.w)) {
         for (uint32_t j = 0; j < rec.y; ++j) order[me.x + j] = rec.x + j;
@@ -96,7 +97,7 @@ __device__ inline void order_node(int64_t b, const WalkNode* __restrict__ wn, ui
         dig[k] = 8u;
         cst[k] = 0u;
         if (k < nc) {
-            const uint4 c = reinterpret_cast<const uint4*>(wn + rec.z + k)[2];
+            const uint4 c = topo[rec.z + k];
             cnt[k] = c.y;
             dig[k] = hilbert_step(me.y, meta_octant(c.w), &cst[k]);
         }
@@ -113,31 +114,31 @@ __device__ inline void order_node(int64_t b, const WalkNode* __restrict__ wn, ui
     }
 }
 
-__global__ __launch_bounds__(256) void k_order_level(uint32_t b0, uint32_t b1, const WalkNode* __restrict__ wn,
+__global__ __launch_bounds__(256) void k_order_level(uint32_t b0, uint32_t b1, const uint4* __restrict__ topo,
                                                      uint2* __restrict__ nord, uint32_t* __restrict__ order)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t b = (int64_t)b0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < (int64_t)b1; b += stride)
-        order_node(b, wn, nord, order);
+        order_node(b, topo, nord, order);
 }
 
 // A run of consecutive small levels [llo, lhi], root side first, in one
 // workgroup; a barrier separates the levels.
 __global__ __launch_bounds__(kSmallLevelThreads) void k_order_small(int llo, int lhi, LevelOffsets off,
-                                                                   const WalkNode* __restrict__ wn,
+                                                                   const uint4* __restrict__ topo,
                                                                    uint2* __restrict__ nord,
                                                                    uint32_t* __restrict__ order)
 {
     for (int l = llo; l <= lhi; ++l) {
         for (int64_t b = (int64_t)off.off[l] + threadIdx.x; b < (int64_t)off.off[l + 1]; b += blockDim.x)
-            order_node(b, wn, nord, order);
+            order_node(b, topo, nord, order);
         __syncthreads();
     }
 }
 
 }  // namespace
 
-void launch_target_order(const uint32_t* level_off_host, const WalkNode* wn, uint2* nord, uint32_t* order,
+void launch_target_order(const uint32_t* level_off_host, const uint4* topo, uint2* nord, uint32_t* order,
                          hipStream_t s)
 {
     LevelOffsets off;
@@ -147,13 +148,13 @@ void launch_target_order(const uint32_t* level_off_host, const WalkNode* wn, uin
         if (off.size(l) <= kSmallLevel) {
             int hi = l;
             while (hi < kMaxLevel && off.size(hi + 1) <= kSmallLevel) ++hi;
-            if (off.off[hi + 1] > off.off[l]) k_order_small<<<1, kSmallLevelThreads, 0, s>>>(l, hi, off, wn, nord, order);
+            if (off.off[hi + 1] > off.off[l]) k_order_small<<<1, kSmallLevelThreads, 0, s>>>(l, hi, off, topo, nord, order);
             l = hi + 1;
             continue;
         }
         int64_t blocks = ((int64_t)off.size(l) + 255) / 256;
         if (blocks > 8192) blocks = 8192;
-        k_order_level<<<(unsigned)blocks, 256, 0, s>>>(off.off[l], off.off[l + 1], wn, nord, order);
+        k_order_level<<<(unsigned)blocks, 256, 0, s>>>(off.off[l], off.off[l + 1], topo, nord, order);
         ++l;
     }
 }

@@ -109,7 +109,8 @@ void launch_bfs_order(const uint8_t* level, int64_t nn, uint64_t* k0, uint32_t* 
 // [level_off_host[l], level_off_host[l+1]), deepest level first.
 void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
                     const uint32_t* first, const uint32_t* count, const uint32_t* nchild, const uint64_t* skeys,
-                    const Particle* sp, const Geom* geom, WalkNode* wn, uint32_t* parent, hipStream_t s);
+                    const Particle* sp, const Geom* geom, WalkNode* wn, uint32_t* parent, uint4* topo,
+                    hipStream_t s);
 // Canonical export: com/mass of pre-order node p from wn[bfs[p]].
 void launch_export_moments(const WalkNode* wn, const uint32_t* bfs, int64_t nn, double* com, double* mass,
                            hipStream_t s);
@@ -152,8 +153,9 @@ void launch_walk(const WalkArgs& a, tc_walk mode, bool count, bool store, hipStr
 void launch_walk_adjoint(const WalkArgs& a, tc_walk mode, hipStream_t s);
 
 // order.hip: the walk's target order (Hilbert order of the particles), from
-// the finished breadth-first records top-down; nord is node-sized scratch.
-void launch_target_order(const uint32_t* level_off_host, const WalkNode* wn, uint2* nord, uint32_t* order,
+// the breadth-first topology records {first, count, child, meta} (written
+// densely by the upward pass) top-down; nord is node-sized scratch.
+void launch_target_order(const uint32_t* level_off_host, const uint4* topo, uint2* nord, uint32_t* order,
                          hipStream_t s);
 
 // adjoint.hip: top-down pass from node gradients to particle gradients.
