@@ -41,18 +41,27 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6    # one FMA per lane per clock: 256 CU x 64 l
 PEAK_FP64_TFLOPS = 78.6
 
 
+def code_hash(path):
+    """sha256 of a C++ source with its comments removed and whitespace collapsed:
+    it changes with the code, not with an edit of a comment."""
+    import hashlib
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return hashlib.sha256(" ".join(src.split()).encode()).hexdigest()
+
+
 def walk_traffic_bytes():
     """HBM bytes per walk launch from the committed rocprofv3 counter summary,
-    or None if the walk source changed since the counters were taken."""
-    import hashlib
+    or None if the walk's code changed since the counters were taken."""
     try:
         kv = {}
         for line in open(TRAFFIC_FILE):
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-        sha = hashlib.sha256(open(WALK_SRC, "rb").read()).hexdigest()
-        if kv.get("walk_hip_sha256") != sha:
+        if kv.get("walk_hip_code_sha256") != code_hash(WALK_SRC):
             return None
         fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
         write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])

@@ -55,8 +55,8 @@ typedef enum { TC_WALK_F32C = 0, TC_WALK_F64 = 1 } tc_walk;
 
 /* tc_forces flags */
 #define TC_COUNT 1u        /* record the interaction count of every target */
-/* TC_STORE_LISTS: record, per wavefront of 64 consecutive targets in key
- * order, every (node, accepting lanes) pair and every opened multi-particle
+/* TC_STORE_LISTS: record, per wavefront of 64 consecutive targets of the
+ * target order (tc_tree_target_order), every (node, accepting lanes) pair and every opened multi-particle
  * leaf of the walk, 16 bytes each, for tc_forces_backward to replay instead of
  * re-walking the tree.  At most 8192 records per wavefront; a wavefront whose
  * records do not fit is re-walked by the backward pass.  The lists are kept

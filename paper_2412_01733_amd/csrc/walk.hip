@@ -1,8 +1,9 @@
 // The Barnes-Hut walk: accelerations and potentials of Eq.(1) with the
 // opening rule of the TreeCode description (section 2).
 //
-// Layout of the work.  One wavefront serves 64 consecutive targets in key
-// order (spatially compact).  It walks the union of the 64 lanes' open sets
+// Layout of the work.  One wavefront serves 64 consecutive targets of the
+// target order, the particles along the Hilbert curve (spatially compact; see
+// order.hip).  It walks the union of the 64 lanes' open sets
 // depth first: a stack in LDS holds groups of sibling nodes together with the
 // 64-bit mask of lanes that opened their parent.  Popping a group stages its
 // <= 8 children into LDS (one lane per child); every active lane then applies
