@@ -3,7 +3,8 @@ storage (seed 1002), eps = 0.005, the launch configuration the benchmark
 times (one tc_build + tc_moments + tc_forces through the C ABI).
 
   * keys, permutation, node table and FP64 moments: bit-exact against the
-    oracle over all 1e7 particles and ~1.5e7 nodes;
+    oracle over all 1e7 particles and ~1.5e7 nodes; the walk's target order a
+    permutation of all 1e7 targets;
   * accelerations and potentials at theta in {0.3, 0.5, 0.8}: on 4096 seeded
     targets the oracle evaluates one by one, F32C median <= 1e-5 and
     p99 <= 1e-4, F64 median <= 1e-13 and p99 <= 1e-11;
@@ -58,6 +59,12 @@ def test_fullsize_tree_bit_exact(big):
     assert (ex["count"].astype(np.int64) == nd["count"]).all()
     assert (ex["mass"] == nd["mass"]).all(), "moments (mass) not bit-exact"
     assert (ex["com"] == nd["com"]).all(), "moments (com) not bit-exact"
+
+
+def test_fullsize_target_order_is_a_permutation(big):
+    """Every one of the 1e7 targets is served by exactly one wavefront."""
+    order = big["tree"].target_order().cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(order), np.arange(N))
 
 
 @pytest.mark.parametrize("theta", [0.3, 0.5, 0.8])
