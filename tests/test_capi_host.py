@@ -63,6 +63,7 @@ def test_argument_validation_without_device():
     assert L.tc_tree_set_timing(None, 1) == m.TC_ERR_INVALID
     assert L.tc_tree_export(None, None, None, None, None, None, None, None, None) == m.TC_ERR_INVALID
     assert L.tc_interaction_counts(None, None, None) == m.TC_ERR_INVALID
+    assert L.tc_tree_target_order(None, None, None) == m.TC_ERR_INVALID
     L.tc_tree_free(None)  # no-op
 
 
