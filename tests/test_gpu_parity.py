@@ -165,6 +165,24 @@ def test_two_body_closed_form():
             assert np.allclose(g["pot"], [-G * 5.0 / q ** 0.5, -G * 2.0 / q ** 0.5], rtol=tol, atol=0)
 
 
+def test_all_particles_coincident():
+    """Every particle at one point: the root cube has L = 1, the tree is a chain
+    of single-child nodes ending in one level-21 leaf holding all of them, and
+    each particle feels a = 0 and phi = -G (M - m_i) / eps from the others."""
+    n, eps, G = 300, 0.25, 1.0
+    x = np.tile(np.array([[0.3, -1.2, 2.5]]), (n, 1))
+    m = np.linspace(1.0, 2.0, n) / n
+    T = oracle.Tree(x, m)
+    for walk in ("f64", "f32c"):
+        g = gpu_run(x, m, 0.5, eps, G, walk=walk)
+        check_tree(g["tree"], T)
+        assert (g["acc"] == 0.0).all()
+        want = -G * (m.sum() - m) / eps
+        tol = 1e-14 if walk == "f64" else 1e-6
+        assert np.allclose(g["pot"], want, rtol=tol, atol=0), np.abs(g["pot"] / want - 1).max()
+        assert (g["counts"] == n - 1).all()
+
+
 def test_determinism_bitwise():
     pos, m = workloads.plummer(20000, 5, dtype=np.float32)
     a = gpu_run(pos, m, 0.5, 0.01)
