@@ -210,7 +210,7 @@ def main():
 
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the TreeCode path here is a single-GPU build "
-              "(targets would shard by contiguous key ranges over a replicated tree); "
+              "(targets would shard by contiguous ranges of the walk's Hilbert target order over a replicated tree); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
