@@ -78,12 +78,12 @@ def stage_bytes(n, nn, p=4):
     write once (no re-reads), for n particles, nn nodes and p-byte inputs."""
     keys = n * (4 * p + (4 * p + 8 + 4 + 4 * p))            # bounds; keys + index + packed record
     sort = n * (8 * (8 + 24) + (4 + 4 * p + 32))             # 8 radix passes (count + move); gather
-    tree = n * (9 + 5 + 8 + 13) + nn * (13 + 13 + 13 + 32 + 8)  # adjacent, counts, scan, emit; node passes
-    # leaf particles and each node's first key (its octant); per node: index, pre-order fields, first child,
-    # children's moments, record, parent link, dense topology record; then the target order: per node its
-    # topology record (read by itself and by its parent) and its {offset, Hilbert state} (written by the
-    # parent, read by itself), per particle its place
-    moments = n * (32 + 8) + nn * (4 + 12 + 4 + 32 + 48 + 4 + 16) + nn * (16 + 16 + 8 + 8) + n * 4
+    tree = n * (9 + 5 + 8 + 13) + nn * (14 + 13 + 13 + 32 + 8)  # adjacent, counts, scan, emit; node passes
+    # leaf particles; per node: index, pre-order fields and octant, first child, children's moments, record,
+    # parent link, dense topology record; then the target order: per node its topology record (read by
+    # itself and by its parent) and its {offset, Hilbert state} (written by the parent, read by itself),
+    # per particle its place
+    moments = n * 32 + nn * (4 + 13 + 4 + 32 + 48 + 4 + 16) + nn * (16 + 16 + 8 + 8) + n * 4
     return dict(keys=keys, sort=sort, tree=tree, moments=moments)
 
 

@@ -123,7 +123,8 @@ __device__ inline int64_t cell_end(const uint64_t* __restrict__ k, int64_t n, in
 __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ k, const int8_t* __restrict__ c,
                                               const uint32_t* __restrict__ pre, int64_t n,
                                               uint8_t* __restrict__ level, uint32_t* __restrict__ first,
-                                              uint32_t* __restrict__ count, uint32_t* __restrict__ next)
+                                              uint32_t* __restrict__ count, uint32_t* __restrict__ next,
+                                              uint8_t* __restrict__ octant)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -135,6 +136,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ k, co
     for (int l = lo; l <= hi; ++l, ++p) {
         int64_t end = (l > cs) ? s + 1 : cell_end(k, n, s, key, l);
         level[p] = (uint8_t)l;
+        octant[p] = l > 0 ? (uint8_t)((key >> (3 * (kMaxLevel - l))) & 7u) : (uint8_t)0;  // key digit at level l
         first[p] = (uint32_t)s;
         count[p] = (uint32_t)(end - s);
         next[p] = pre[end];
@@ -198,10 +200,11 @@ void launch_node_counts(const int8_t* c, int64_t n, uint32_t* cnt, uint32_t* lev
 }
 
 void launch_emit_nodes(const uint64_t* skeys, const int8_t* c, const uint32_t* pre, int64_t n,
-                       uint8_t* level, uint32_t* first, uint32_t* count, uint32_t* next, hipStream_t s)
+                       uint8_t* level, uint32_t* first, uint32_t* count, uint32_t* next, uint8_t* octant,
+                       hipStream_t s)
 {
     if (n == 0) return;
-    k_emit<<<grid_for(n, 256), 256, 0, s>>>(skeys, c, pre, n, level, first, count, next);
+    k_emit<<<grid_for(n, 256), 256, 0, s>>>(skeys, c, pre, n, level, first, count, next, octant);
 }
 
 void launch_count_children(const uint8_t* level, const uint32_t* count, const uint32_t* next, int64_t nn,

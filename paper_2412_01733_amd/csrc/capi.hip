@@ -81,7 +81,7 @@ struct tc_tree {
     uint32_t* perm = nullptr;
     Buf sort_temp, scan_temp, bounds_part;
     // node-sized
-    Buf level, first, count, next, nchild, bfs, nk0, nk1, nv0, nv1, node_sort_temp, wn, diag_temp, parent;
+    Buf level, first, count, next, nchild, bfs, nk0, nk1, nv0, nv1, node_sort_temp, wn, diag_temp, parent, octant;
     Buf topo, nord, order;     // the walk's target order (particle-sized); dense topology and scratch (node-sized)
     // adjoint and leapfrog
     Buf node_grad, uc, part_grad, target_grad, step_temp;
@@ -315,6 +315,7 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     t->nn = nn;
     const size_t m4 = (size_t)nn * 4;
     TC_TRY(ensure(t, t->level, (size_t)nn, s));
+    TC_TRY(ensure(t, t->octant, (size_t)nn, s));
     TC_TRY(ensure(t, t->first, m4, s));
     TC_TRY(ensure(t, t->count, m4, s));
     TC_TRY(ensure(t, t->next, m4, s));
@@ -330,7 +331,7 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     TC_TRY(ensure(t, t->topo, (size_t)nn * 16, s));
 
     launch_emit_nodes(t->skeys, P<int8_t>(t->c), P<uint32_t>(t->pre), n, P<uint8_t>(t->level), P<uint32_t>(t->first),
-                      P<uint32_t>(t->count), P<uint32_t>(t->next), s);
+                      P<uint32_t>(t->count), P<uint32_t>(t->next), P<uint8_t>(t->octant), s);
     launch_count_children(P<uint8_t>(t->level), P<uint32_t>(t->count), P<uint32_t>(t->next), nn,
                           P<uint32_t>(t->nchild), s);
     launch_bfs_order(P<uint8_t>(t->level), nn, P<uint64_t>(t->nk0), P<uint32_t>(t->nv0), P<uint64_t>(t->nk1),
@@ -346,7 +347,7 @@ tc_status moments_impl(tc_tree* t, hipStream_t s)
     if (t->n > 0) {
         stage_begin(t, kStMoments, s);
         launch_moments(t->host->level_off, t->bfs_to_pre, P<uint32_t>(t->bfs), P<uint32_t>(t->first),
-                       P<uint32_t>(t->count), P<uint32_t>(t->nchild), t->skeys, P<Particle>(t->sp), t->geom,
+                       P<uint32_t>(t->count), P<uint32_t>(t->nchild), t->skeys, P<uint8_t>(t->octant), P<Particle>(t->sp), t->geom,
                        P<WalkNode>(t->wn), P<uint32_t>(t->parent), P<uint4>(t->topo), s);
         TC_TRY(ensure(t, t->nord, (size_t)t->nn * sizeof(uint2), s));
         TC_TRY(ensure(t, t->order, (size_t)t->n * 4, s));
@@ -714,7 +715,7 @@ void tc_tree_free(tc_tree* t)
     Buf* bufs[] = {&t->keys0, &t->keys1, &t->vals0, &t->vals1, &t->rec, &t->sp, &t->c, &t->cnt,
                    &t->pre, &t->sorted_counts, &t->diag_part, &t->sort_temp, &t->scan_temp, &t->bounds_part,
                    &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->bfs, &t->nk0, &t->nk1,
-                   &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->parent, &t->topo, &t->nord, &t->order, &t->node_grad,
+                   &t->nv0, &t->nv1, &t->node_sort_temp, &t->wn, &t->diag_temp, &t->parent, &t->topo, &t->nord, &t->order, &t->octant, &t->node_grad,
                    &t->uc, &t->part_grad, &t->target_grad, &t->step_temp, &t->lists, &t->list_len, &t->small};
     for (Buf* b : bufs) release(t, *b);
     for (auto& e : t->ev)

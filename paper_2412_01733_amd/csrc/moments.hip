@@ -42,7 +42,8 @@ __device__ inline void cell_centre(uint64_t key, int level, const Geom* g, doubl
 __device__ inline void moments_node(int64_t b, int l, const uint32_t* __restrict__ bfs_to_pre,
                                     const uint32_t* __restrict__ bfs, const uint32_t* __restrict__ first,
                                     const uint32_t* __restrict__ count, const uint32_t* __restrict__ nchild,
-                                    const uint64_t* __restrict__ skeys, const Particle* __restrict__ sp,
+                                    const uint64_t* __restrict__ skeys, const uint8_t* __restrict__ octant,
+                                    const Particle* __restrict__ sp,
                                     const Geom* __restrict__ g, WalkNode* __restrict__ wn,
                                     uint32_t* __restrict__ parent, uint4* __restrict__ topo)
 {
@@ -96,9 +97,9 @@ __device__ inline void moments_node(int64_t b, int l, const uint32_t* __restrict
     }
     if (centre) cell_centre(skeys[f], l, g, X);
     const bool single = nc == 0 && c == 1;
-    const uint32_t octant = l > 0 ? (uint32_t)(skeys[f] >> (3 * (kMaxLevel - l))) & 7u : 0u;
+    const uint32_t oc = octant[p];
     const uint32_t meta = nc | ((uint32_t)l << 8) | (single ? (1u << 13) : 0u) | (nc == 0 ? (1u << 16) : 0u) |
-                          (single ? (1u << 17) : 0u) | (octant << 18);
+                          (single ? (1u << 17) : 0u) | (oc << 18);
     uint4* o = reinterpret_cast<uint4*>(wn + b);
     o[0] = make_uint4(__double2loint(X[0]), __double2hiint(X[0]), __double2loint(X[1]), __double2hiint(X[1]));
     o[1] = make_uint4(__double2loint(X[2]), __double2hiint(X[2]), __double2loint(M), __double2hiint(M));
@@ -109,9 +110,9 @@ __device__ inline void moments_node(int64_t b, int l, const uint32_t* __restrict
 #define MOM_ARGS                                                                                                  \
     const uint32_t *__restrict__ bfs_to_pre, const uint32_t *__restrict__ bfs, const uint32_t *__restrict__ first, \
         const uint32_t *__restrict__ count, const uint32_t *__restrict__ nchild, const uint64_t *__restrict__ skeys, \
-        const Particle *__restrict__ sp, const Geom *__restrict__ g, WalkNode *__restrict__ wn,                  \
+        const uint8_t *__restrict__ octant, const Particle *__restrict__ sp, const Geom *__restrict__ g, WalkNode *__restrict__ wn,                  \
         uint32_t *__restrict__ parent, uint4 *__restrict__ topo
-#define MOM_PASS bfs_to_pre, bfs, first, count, nchild, skeys, sp, g, wn, parent, topo
+#define MOM_PASS bfs_to_pre, bfs, first, count, nchild, skeys, octant, sp, g, wn, parent, topo
 
 // One level with many nodes: one thread per node.
 __global__ __launch_bounds__(256) void k_moments_level(int l, uint32_t b0, uint32_t b1, MOM_ARGS)
@@ -153,7 +154,8 @@ __global__ __launch_bounds__(256) void k_export_moments(const WalkNode* __restri
 
 void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
                     const uint32_t* first, const uint32_t* count, const uint32_t* nchild, const uint64_t* skeys,
-                    const Particle* sp, const Geom* g, WalkNode* wn, uint32_t* parent, uint4* topo, hipStream_t s)
+                    const uint8_t* octant, const Particle* sp, const Geom* g, WalkNode* wn, uint32_t* parent,
+                    uint4* topo, hipStream_t s)
 {
     LevelOffsets off;
     for (int l = 0; l <= kLevels; ++l) off.off[l] = level_off_host[l];

@@ -95,7 +95,7 @@ void launch_adjacent_levels(const uint64_t* skeys, int64_t n, int8_t* c, hipStre
 // level_hist: [kLevels + 2] = nodes per level, leaves, multi-particle leaves
 void launch_node_counts(const int8_t* c, int64_t n, uint32_t* cnt, uint32_t* level_hist, hipStream_t s);
 void launch_emit_nodes(const uint64_t* skeys, const int8_t* c, const uint32_t* pre, int64_t n,
-                       uint8_t* level, uint32_t* first, uint32_t* count, uint32_t* next,
+                       uint8_t* level, uint32_t* first, uint32_t* count, uint32_t* next, uint8_t* octant,
                        hipStream_t s);
 void launch_count_children(const uint8_t* level, const uint32_t* count, const uint32_t* next,
                            int64_t nn, uint32_t* nchild, hipStream_t s);
@@ -109,8 +109,8 @@ void launch_bfs_order(const uint8_t* level, int64_t nn, uint64_t* k0, uint32_t* 
 // [level_off_host[l], level_off_host[l+1]), deepest level first.
 void launch_moments(const uint32_t* level_off_host, const uint32_t* bfs_to_pre, const uint32_t* bfs,
                     const uint32_t* first, const uint32_t* count, const uint32_t* nchild, const uint64_t* skeys,
-                    const Particle* sp, const Geom* geom, WalkNode* wn, uint32_t* parent, uint4* topo,
-                    hipStream_t s);
+                    const uint8_t* octant, const Particle* sp, const Geom* geom, WalkNode* wn, uint32_t* parent,
+                    uint4* topo, hipStream_t s);
 // Canonical export: com/mass of pre-order node p from wn[bfs[p]].
 void launch_export_moments(const WalkNode* wn, const uint32_t* bfs, int64_t nn, double* com, double* mass,
                            hipStream_t s);
