@@ -72,7 +72,11 @@ typedef void* (*tc_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*tc_free_fn)(void* ptr, void* stream, void* ctx);
 
 /* Install the allocator used by handles created afterwards (process-wide).
- * Passing NULL for both restores the default (hipMalloc / hipFree).
+ * Passing NULL for both restores the default (hipMalloc / hipFree).  A handle
+ * frees a buffer it grows past on the stream of the growing call, and frees
+ * everything in tc_tree_free after its enqueued work is done; a stream-ordered
+ * allocator (the Python binding installs torch's caching allocator) needs no
+ * device synchronisation for either.
  * Errors: TC_ERR_INVALID if exactly one of alloc/free is NULL. */
 tc_status tc_set_allocator(tc_alloc_fn alloc, tc_free_fn free_fn, void* ctx);
 
@@ -87,7 +91,10 @@ tc_status tc_set_allocator(tc_alloc_fn alloc, tc_free_fn free_fn, void* ctx);
  * BLOCKS once: the node count is read back to size the node arrays.
  * Errors: TC_ERR_INVALID (null pointers with n > 0, n out of range, bad
  * dtype), TC_ERR_INPUT (non-finite position, negative or non-finite mass),
- * TC_ERR_NOMEM, TC_ERR_OVERFLOW (>= 2^32 nodes), TC_ERR_DEVICE. */
+ * TC_ERR_NOMEM, TC_ERR_OVERFLOW (>= 2^32 nodes), TC_ERR_DEVICE.  At its
+ * synchronisation a rebuild also reports the status of the previous walk on
+ * the handle (see tc_tree_stats): TC_ERR_OVERFLOW or TC_ERR_DEVICE if that walk
+ * was incomplete, in which case the rebuild has not run. */
 tc_status tc_build(const void* pos, const void* mass, int64_t n, tc_dtype dtype,
                    void* stream, tc_tree** tree);
 
@@ -168,11 +175,22 @@ typedef struct {
                                 (-1 if not recorded) */
     uint32_t lists_stored;   /* 1 if the last tc_forces stored interaction lists (TC_STORE_LISTS
                                 within the list budget), else 0 */
-    uint32_t reserved;
+    uint32_t max_stack;      /* TC_COUNT: deepest traversal stack of any wavefront (groups) */
+    uint64_t group_pops;     /* TC_COUNT: sibling groups taken from the stacks, summed over wavefronts */
+    uint64_t visits_no_accept;   /* TC_COUNT: node evaluations at which no active lane accepts */
+    uint64_t visits_all_accept;  /* TC_COUNT: node evaluations at which every active lane accepts */
+    uint64_t visits_box_open;    /* TC_COUNT: evaluations the per-wavefront box test shows every
+                                    target must open (the node is nearer than s/theta to the box) */
+    uint64_t visits_box_accept;  /* TC_COUNT: evaluations the box test shows every target accepts */
 } tc_stats;
 
-/* Fill *out.  Synchronises `stream` when diagnostics or timings are pending.
- * Errors: TC_ERR_INVALID (null pointer). */
+/* Fill *out.  Synchronises `stream` when diagnostics, timings or a walk's
+ * status are pending.
+ * Errors: TC_ERR_INVALID (null pointer); after filling *out, the status of
+ * the walks since the last check: TC_ERR_OVERFLOW if a traversal stack would
+ * have overflowed (terms dropped), TC_ERR_DEVICE if a walk met a node with
+ * more than 8 children.  Neither can happen for a tree built by tc_build: the
+ * traversal stack is sized from the depth bound of the octree. */
 tc_status tc_tree_stats(tc_tree* tree, tc_stats* out, void* stream);
 
 /* Record per-stage durations with HIP events on the call's stream (off by
@@ -202,8 +220,9 @@ tc_status tc_tree_target_order(const tc_tree* tree, uint32_t* order, void* strea
  * Errors: TC_ERR_INVALID, TC_ERR_STATE (no counted walk). */
 tc_status tc_interaction_counts(const tc_tree* tree, uint32_t* counts, void* stream);
 
-/* Release a handle and everything it owns (NULL is a no-op).  Synchronises
- * the device before freeing. */
+/* Release a handle and everything it owns (NULL is a no-op).  Waits for the
+ * work the handle's calls enqueued (an event recorded by each call), not for
+ * the whole device, then frees. */
 void tc_tree_free(tc_tree* tree);
 
 /* Message of the last error on this thread ("" if none). */

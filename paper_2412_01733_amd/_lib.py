@@ -47,7 +47,12 @@ class TcStats(ctypes.Structure):
         ("ang_momentum", ctypes.c_double * 3),
         ("stage_ms", ctypes.c_float * 8),
         ("lists_stored", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("max_stack", ctypes.c_uint32),
+        ("group_pops", ctypes.c_uint64),
+        ("visits_no_accept", ctypes.c_uint64),
+        ("visits_all_accept", ctypes.c_uint64),
+        ("visits_box_open", ctypes.c_uint64),
+        ("visits_box_accept", ctypes.c_uint64),
     ]
 
 

@@ -58,7 +58,7 @@ struct HostMirror {
     uint32_t level_off[kLevels + 1];
     double diag[4];
     unsigned long long inter;
-    unsigned long long visits[2];
+    unsigned long long visits[kNumVisitCounters];
     double step[10];
     uint32_t status;
 };
@@ -94,7 +94,7 @@ struct tc_tree {
     double* diag_out = nullptr;
     double* step_out = nullptr;  // [10]
     unsigned long long* inter_total = nullptr;
-    unsigned long long* visits = nullptr;      // [2]
+    unsigned long long* visits = nullptr;      // [kNumVisitCounters]
     uint32_t* status = nullptr;
 
     HostMirror* host = nullptr;
@@ -112,6 +112,8 @@ struct tc_tree {
     bool timing = false;
     hipEvent_t ev[2 * kNumStages] = {};
     bool ev_used[kNumStages] = {};
+    hipEvent_t done = nullptr;  // recorded after the last work each call enqueues (tc_tree_free waits on it)
+    bool walk_status_pending = false;  // a walk's status word is on its way to host->status
 };
 
 namespace {
@@ -217,7 +219,7 @@ tc_status create_tree(tc_tree** out, hipStream_t s)
     t->inter_total = (unsigned long long*)p;
     p += 8;
     t->visits = (unsigned long long*)p;
-    p += 16;
+    p += 8 * kNumVisitCounters;
     t->level_hist = (uint32_t*)p;
     p += 4 * (kLevels + 2);
     t->status = (uint32_t*)p;
@@ -228,7 +230,36 @@ tc_status create_tree(tc_tree** out, hipStream_t s)
         return fail(TC_ERR_NOMEM, "pinned host allocation failed");
     }
     memset(t->host, 0, sizeof(HostMirror));
+    if (hipEventCreateWithFlags(&t->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(t->host);
+        release(t, t->small);
+        delete t;
+        return fail(TC_ERR_DEVICE, "event creation failed");
+    }
     *out = t;
+    return TC_OK;
+}
+
+// Record the handle's completion event after the work a call enqueued on s.
+tc_status mark_done(tc_tree* t, hipStream_t s, tc_status st)
+{
+    if (t && t->done && hipEventRecord(t->done, s) != hipSuccess) (void)hipGetLastError();
+    return st;
+}
+
+// Status word of the walks (bit 0: a traversal stack would have overflowed, so
+// terms were dropped; bit 1: a node with more than 8 children, i.e. a corrupt
+// tree).  Neither can happen for a tree built by tc_build (the stack bound is
+// proven in walk.hip); both are checked wherever the host synchronises anyway.
+tc_status walk_status_error(tc_tree* t)
+{
+    if (!t->walk_status_pending) return TC_OK;
+    t->walk_status_pending = false;
+    const uint32_t st = t->host->status;
+    t->host->status = 0;
+    if (st & 1u) return fail(TC_ERR_OVERFLOW, "a walk on this handle overflowed its traversal stack; its outputs are incomplete");
+    if (st & 2u) return fail(TC_ERR_DEVICE, "a walk on this handle met a node with more than 8 children (corrupt tree)");
     return TC_OK;
 }
 
@@ -298,6 +329,8 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     HIP_TRY(hipMemcpyAsync(&t->host->total, P<uint32_t>(t->pre) + n, 4, hipMemcpyDeviceToHost, s));
     TC_TRY(check_launch("tree counts"));
     HIP_TRY(hipStreamSynchronize(s));
+    // the previous walk on this handle, enqueued before this build on the same stream, is complete
+    TC_TRY(walk_status_error(t));
     t->geom_host = t->host->geom;
     if (t->geom_host.bad & 1u) return fail(TC_ERR_INPUT, "non-finite particle position");
     if (t->geom_host.bad & 2u) return fail(TC_ERR_INPUT, "negative or non-finite particle mass");
@@ -422,7 +455,7 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     }
 
     launch_fill_u32(t->status, 1, 0u, s);
-    if (t->counted) launch_fill_u32((uint32_t*)t->visits, 4, 0u, s);
+    if (t->counted) launch_fill_u32((uint32_t*)t->visits, 2 * kNumVisitCounters, 0u, s);
     stage_begin(t, kStWalk, s);
     launch_walk(a, mode, t->counted, store, s);
     stage_end(t, kStWalk, s);
@@ -434,9 +467,10 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
     TC_TRY(check_launch("diagnostics"));
     HIP_TRY(hipMemcpyAsync(t->host->diag, t->diag_out, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&t->host->status, t->status, 4, hipMemcpyDeviceToHost, s));
+    t->walk_status_pending = true;
     if (t->counted) {
         HIP_TRY(hipMemcpyAsync(&t->host->inter, t->inter_total, 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(t->host->visits, t->visits, 16, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(t->host->visits, t->visits, 8 * kNumVisitCounters, hipMemcpyDeviceToHost, s));
     }
     t->diag_pending = true;
     t->state |= 4u;
@@ -473,6 +507,8 @@ tc_status backward_impl(tc_tree* t, const void* g_acc, const void* g_pot, void* 
     launch_walk_adjoint(a, t->last_mode, s);
     stage_end(t, kStBwdWalk, s);
     TC_TRY(check_launch("adjoint walk"));
+    HIP_TRY(hipMemcpyAsync(&t->host->status, t->status, 4, hipMemcpyDeviceToHost, s));
+    t->walk_status_pending = true;
     stage_begin(t, kStBwdDown, s);
     launch_adjoint_down(t->host->level_off, P<WalkNode>(t->wn), P<uint32_t>(t->parent), a.node_grad, P<double>(t->uc),
                         a.sp, t->perm, a.target_grad, a.part_grad, g_pos, g_mass,
@@ -481,6 +517,31 @@ tc_status backward_impl(tc_tree* t, const void* g_acc, const void* g_pot, void* 
     TC_TRY(check_launch("adjoint down-pass"));
     return TC_OK;
 }
+
+tc_status leapfrog_impl(tc_tree* t, void* pos, void* vel, const void* mass, void* acc, void* pot, int64_t n,
+                        tc_dtype dtype, double tau, double theta, double eps, double G, tc_walk mode, hipStream_t s)
+{
+    const bool acc64 = mode == TC_WALK_F64;
+    launch_kick_drift(pos, vel, acc, n, dtype, acc64, tau, s);            // Eqs.(2), (3)
+    TC_TRY(check_launch("kick-drift"));
+    TC_TRY(build_impl(t, pos, mass, n, dtype, s));                       // Eq.(4): rebuild ...
+    TC_TRY(moments_impl(t, s));
+    TC_TRY(forces_impl(t, theta, eps, G, mode, 0u, acc, pot, s));        // ... and evaluate
+    launch_kick(vel, acc, n, dtype, acc64, tau, s);                      // Eq.(5)
+    TC_TRY(check_launch("kick"));
+    if (n > 0) {
+        TC_TRY(ensure(t, t->step_temp, step_diag_temp_bytes(), s));
+        launch_step_diag(pos, vel, mass, pot, n, dtype, acc64, t->step_temp.p, t->step_out, s);
+        TC_TRY(check_launch("step diagnostics"));
+        HIP_TRY(hipMemcpyAsync(t->host->step, t->step_out, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
+        t->step_pending = true;
+    } else {
+        for (int k = 0; k < 10; ++k) t->host->step[k] = 0.0;
+    }
+    t->step_valid = true;
+    return TC_OK;
+}
+
 
 }  // namespace
 
@@ -510,7 +571,7 @@ tc_status tc_build(const void* pos, const void* mass, int64_t n, tc_dtype dtype,
     } else {
         TC_TRY(check_device(*tree));
     }
-    return build_impl(*tree, pos, mass, n, dtype, s);
+    return mark_done(*tree, s, build_impl(*tree, pos, mass, n, dtype, s));
 }
 
 tc_status tc_moments(tc_tree* t, void* stream)
@@ -519,7 +580,7 @@ tc_status tc_moments(tc_tree* t, void* stream)
     if (!t) return fail(TC_ERR_INVALID, "tc_moments: tree is NULL");
     if (!(t->state & 1u)) return fail(TC_ERR_STATE, "tc_moments: no successful tc_build on this handle");
     TC_TRY(check_device(t));
-    return moments_impl(t, (hipStream_t)stream);
+    return mark_done(t, (hipStream_t)stream, moments_impl(t, (hipStream_t)stream));
 }
 
 tc_status tc_forces(tc_tree* t, double theta, double eps, double G, tc_walk mode, uint32_t flags, void* acc,
@@ -535,7 +596,7 @@ tc_status tc_forces(tc_tree* t, double theta, double eps, double G, tc_walk mode
     if (t->n > 0 && !acc) return fail(TC_ERR_INVALID, "tc_forces: acc must be non-NULL");
     if ((t->state & 3u) != 3u) return fail(TC_ERR_STATE, "tc_forces: call tc_build and tc_moments first");
     TC_TRY(check_device(t));
-    return forces_impl(t, theta, eps, G, mode, flags, acc, pot, (hipStream_t)stream);
+    return mark_done(t, (hipStream_t)stream, forces_impl(t, theta, eps, G, mode, flags, acc, pot, (hipStream_t)stream));
 }
 
 tc_status tc_forces_backward(tc_tree* t, const void* g_acc, const void* g_pot, void* g_pos, void* g_mass,
@@ -546,7 +607,7 @@ tc_status tc_forces_backward(tc_tree* t, const void* g_acc, const void* g_pot, v
     if (!(t->state & 4u)) return fail(TC_ERR_STATE, "tc_forces_backward: no tc_forces since the last tc_build");
     if (t->n > 0 && !g_acc) return fail(TC_ERR_INVALID, "tc_forces_backward: g_acc must be non-NULL");
     TC_TRY(check_device(t));
-    return backward_impl(t, g_acc, g_pot, g_pos, g_mass, (hipStream_t)stream);
+    return mark_done(t, (hipStream_t)stream, backward_impl(t, g_acc, g_pot, g_pos, g_mass, (hipStream_t)stream));
 }
 
 tc_status tc_leapfrog_step(tc_tree** tree, void* pos, void* vel, const void* mass, void* acc, void* pot,
@@ -565,32 +626,14 @@ tc_status tc_leapfrog_step(tc_tree** tree, void* pos, void* vel, const void* mas
     if (!is_finite(G)) return fail(TC_ERR_INVALID, "tc_leapfrog_step: G must be finite");
     if (mode != TC_WALK_F32C && mode != TC_WALK_F64) return fail(TC_ERR_INVALID, "tc_leapfrog_step: bad walk mode");
     hipStream_t s = (hipStream_t)stream;
-    const bool acc64 = mode == TC_WALK_F64;
     if (!*tree) {
         TC_TRY(create_tree(tree, s));
     } else {
         TC_TRY(check_device(*tree));
     }
-    tc_tree* t = *tree;
-    launch_kick_drift(pos, vel, acc, n, dtype, acc64, tau, s);            // Eqs.(2), (3)
-    TC_TRY(check_launch("kick-drift"));
-    TC_TRY(build_impl(t, pos, mass, n, dtype, s));                       // Eq.(4): rebuild ...
-    TC_TRY(moments_impl(t, s));
-    TC_TRY(forces_impl(t, theta, eps, G, mode, 0u, acc, pot, s));        // ... and evaluate
-    launch_kick(vel, acc, n, dtype, acc64, tau, s);                      // Eq.(5)
-    TC_TRY(check_launch("kick"));
-    if (n > 0) {
-        TC_TRY(ensure(t, t->step_temp, step_diag_temp_bytes(), s));
-        launch_step_diag(pos, vel, mass, pot, n, dtype, acc64, t->step_temp.p, t->step_out, s);
-        TC_TRY(check_launch("step diagnostics"));
-        HIP_TRY(hipMemcpyAsync(t->host->step, t->step_out, 10 * sizeof(double), hipMemcpyDeviceToHost, s));
-        t->step_pending = true;
-    } else {
-        for (int k = 0; k < 10; ++k) t->host->step[k] = 0.0;
-    }
-    t->step_valid = true;
-    return TC_OK;
+    return mark_done(*tree, s, leapfrog_impl(*tree, pos, vel, mass, acc, pot, n, dtype, tau, theta, eps, G, mode, s));
 }
+
 
 tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
 {
@@ -599,7 +642,7 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
     memset(out, 0, sizeof *out);
     bool any_ev = false;
     for (int i = 0; i < kNumStages; ++i) any_ev |= t->ev_used[i];
-    if (t->diag_pending || t->build_pending || t->step_pending || any_ev) {
+    if (t->diag_pending || t->build_pending || t->step_pending || t->walk_status_pending || any_ev) {
         TC_TRY(check_device(t));
         HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
         t->diag_pending = false;
@@ -628,6 +671,14 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
         out->interactions = t->counted ? t->host->inter : 0;
         out->node_visits = t->counted ? t->host->visits[0] : 0;
         out->lane_visits = t->counted ? t->host->visits[1] : 0;
+        if (t->counted) {
+            out->group_pops = t->host->visits[2];
+            out->visits_no_accept = t->host->visits[3];
+            out->visits_all_accept = t->host->visits[4];
+            out->visits_box_open = t->host->visits[5];
+            out->visits_box_accept = t->host->visits[6];
+            out->max_stack = (uint32_t)t->host->visits[7];
+        }
     }
     if (t->step_valid) {
         out->kinetic = t->host->step[0];
@@ -645,9 +696,7 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
             else (void)hipGetLastError();
         }
     }
-    if (t->host->status & 1u) return fail(TC_ERR_OVERFLOW, "walk stack overflow");
-    if (t->host->status & 2u) return fail(TC_ERR_DEVICE, "corrupt tree: a node with more than 8 children");
-    return TC_OK;
+    return walk_status_error(t);
 }
 
 tc_status tc_tree_set_timing(tc_tree* t, int on)
@@ -684,7 +733,7 @@ tc_status tc_tree_export(const tc_tree* t, uint64_t* keys, uint32_t* perm, uint8
         launch_export_moments(P<WalkNode>(t->wn), P<uint32_t>(t->bfs), (int64_t)nn, com, mass, s);
         TC_TRY(check_launch("export"));
     }
-    return TC_OK;
+    return mark_done(const_cast<tc_tree*>(t), s, TC_OK);
 }
 
 tc_status tc_tree_target_order(const tc_tree* t, uint32_t* order, void* stream)
@@ -695,7 +744,7 @@ tc_status tc_tree_target_order(const tc_tree* t, uint32_t* order, void* stream)
     TC_TRY(check_device(t));
     if (t->n == 0) return TC_OK;
     HIP_TRY(hipMemcpyAsync(order, t->order.p, (size_t)t->n * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
-    return TC_OK;
+    return mark_done(const_cast<tc_tree*>(t), (hipStream_t)stream, TC_OK);
 }
 
 tc_status tc_interaction_counts(const tc_tree* t, uint32_t* counts, void* stream)
@@ -705,13 +754,14 @@ tc_status tc_interaction_counts(const tc_tree* t, uint32_t* counts, void* stream
     if (!(t->state & 4u) || !t->counted) return fail(TC_ERR_STATE, "tc_interaction_counts: no counted tc_forces");
     TC_TRY(check_device(t));
     launch_scatter_counts(P<uint32_t>(t->sorted_counts), t->perm, t->n, counts, (hipStream_t)stream);
-    return check_launch("counts");
+    return mark_done(const_cast<tc_tree*>(t), (hipStream_t)stream, check_launch("counts"));
 }
 
 void tc_tree_free(tc_tree* t)
 {
     if (!t) return;
-    (void)hipDeviceSynchronize();
+    // wait for the work the handle's calls enqueued (on whichever stream), not the whole device
+    if (t->done && hipEventSynchronize(t->done) != hipSuccess) (void)hipGetLastError();
     Buf* bufs[] = {&t->keys0, &t->keys1, &t->vals0, &t->vals1, &t->rec, &t->sp, &t->c, &t->cnt,
                    &t->pre, &t->sorted_counts, &t->diag_part, &t->sort_temp, &t->scan_temp, &t->bounds_part,
                    &t->level, &t->first, &t->count, &t->next, &t->nchild, &t->bfs, &t->nk0, &t->nk1,
@@ -720,6 +770,7 @@ void tc_tree_free(tc_tree* t)
     for (Buf* b : bufs) release(t, *b);
     for (auto& e : t->ev)
         if (e) (void)hipEventDestroy(e);
+    if (t->done) (void)hipEventDestroy(t->done);
     if (t->host) (void)hipHostFree(t->host);
     delete t;
 }

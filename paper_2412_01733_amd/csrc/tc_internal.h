@@ -131,7 +131,7 @@ struct WalkArgs {
     uint32_t* counts;       // sorted order (counting walk only)
     double* diag;           // [waves, 4] partials of sum m a, sum m |a|
     uint32_t* status;       // bit 0: stack overflow (never expected)
-    unsigned long long* visits;  // counting walk: [0] wave-level node evaluations, [1] sum of active lanes
+    unsigned long long* visits;  // counting walk: [kNumVisitCounters], see tc_stats (node_visits ... max_stack)
     // adjoint walk only
     const void* g_acc;      // dL/da [n,3], caller order, walk precision
     const void* g_pot;      // dL/dphi [n] or NULL
@@ -145,6 +145,10 @@ struct WalkArgs {
     uint32_t* list_len;     // [waves]: records of the wave, or kListInvalid if they did not fit
     uint32_t list_cap;      // records per wave
 };
+// counting walk: node evaluations, active lanes, group pops, evaluations with no
+// accepting lane, with every active lane accepting, decided "all open" and "all
+// accept" by the per-wave box test, deepest stack (atomic max)
+constexpr int kNumVisitCounters = 8;
 constexpr uint32_t kListCap = 8192;                     // records per wave (128 KiB)
 constexpr uint32_t kListInvalid = 0xFFFFFFFFu;
 constexpr uint64_t kListMaxBytes = 4ull << 30;          // lists are stored only up to this size

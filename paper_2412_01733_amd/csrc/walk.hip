@@ -278,7 +278,22 @@ void k_walk(WalkArgs a)
     float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
     R bx = 0, by = 0, bz = 0, bp = 0;
     uint32_t nint = 0;
-    uint64_t vis_nodes = 0, vis_lanes = 0;  // counting walk: wave-level node evaluations
+    // counting walk: wave-level node evaluations and how they were decided
+    uint64_t vis_nodes = 0, vis_lanes = 0, vis_groups = 0, vis_noacc = 0, vis_allacc = 0, vis_boxopen = 0,
+             vis_boxacc = 0;
+    int max_sp = 0;
+    // counting walk: bounding box of the wavefront's targets (anchor-relative) for the box test
+    R bnx = 0, bny = 0, bnz = 0, bxx = 0, bxy = 0, bxz = 0;
+    if constexpr (COUNT) {
+        bnx = valid ? px : (R)INFINITY; bny = valid ? py : (R)INFINITY; bnz = valid ? pz : (R)INFINITY;
+        bxx = valid ? px : (R)-INFINITY; bxy = valid ? py : (R)-INFINITY; bxz = valid ? pz : (R)-INFINITY;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            bnx = fmin(bnx, __shfl_xor(bnx, o, 64)); bny = fmin(bny, __shfl_xor(bny, o, 64));
+            bnz = fmin(bnz, __shfl_xor(bnz, o, 64)); bxx = fmax(bxx, __shfl_xor(bxx, o, 64));
+            bxy = fmax(bxy, __shfl_xor(bxy, o, 64)); bxz = fmax(bxz, __shfl_xor(bxz, o, 64));
+        }
+    }
 
     int sp = 0;
     bool stack_over = false;
@@ -499,6 +514,8 @@ void k_walk(WalkArgs a)
         if constexpr (COUNT) {
             vis_nodes += nc;
             vis_lanes += (uint64_t)nc * (uint64_t)__popcll(mask);
+            vis_groups += 1;
+            max_sp = max(max_sp, sp + 1);
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -511,6 +528,24 @@ void k_walk(WalkArgs a)
             if ((ovl_m >> k) & 1ull) in_m = __ballot((su - h.first) < h.count);
             const uint64_t far_m = __ballot(d2 > h.tau);
             const uint64_t am = mask & far_m & ~in_m;
+            if constexpr (COUNT) {
+                vis_noacc += am == 0;
+                vis_allacc += am == mask;
+                // box test: every target of the wave lies in [bn, bx]; with a relative
+                // margin for the rounding of both distances, a node farther than s/theta
+                // from the whole box is accepted by every lane, one nearer from all of it
+                // is opened by every lane
+                const R ex = fmax(fmax(bnx - h.x, h.x - bxx), (R)0);
+                const R ey = fmax(fmax(bny - h.y, h.y - bxy), (R)0);
+                const R ez = fmax(fmax(bnz - h.z, h.z - bxz), (R)0);
+                const R fx = fmax(fabs(h.x - bnx), fabs(h.x - bxx));
+                const R fy = fmax(fabs(h.y - bny), fabs(h.y - bxy));
+                const R fz = fmax(fabs(h.z - bnz), fabs(h.z - bxz));
+                const R dmin2 = ex * ex + ey * ey + ez * ez, dmax2 = fx * fx + fy * fy + fz * fz;
+                const R marg = (R)1 + (R)0x1p-18;
+                vis_boxopen += h.tau >= (R)0 && dmax2 * marg < h.tau;
+                vis_boxacc += !((ovl_m >> k) & 1ull) && (h.tau < (R)0 || dmin2 > h.tau * marg);
+            }
             if constexpr (!ADJ) {
                 if (__builtin_amdgcn_inverse_ballot_w64(am)) {
                     const R ri = rsqrt_any(d2 + eps2);
@@ -616,6 +651,12 @@ void k_walk(WalkArgs a)
         if constexpr (COUNT) {
             atomicAdd(&a.visits[0], (unsigned long long)vis_nodes);
             atomicAdd(&a.visits[1], (unsigned long long)vis_lanes);
+            atomicAdd(&a.visits[2], (unsigned long long)vis_groups);
+            atomicAdd(&a.visits[3], (unsigned long long)vis_noacc);
+            atomicAdd(&a.visits[4], (unsigned long long)vis_allacc);
+            atomicAdd(&a.visits[5], (unsigned long long)vis_boxopen);
+            atomicAdd(&a.visits[6], (unsigned long long)vis_boxacc);
+            atomicMax(&a.visits[7], (unsigned long long)max_sp);
         }
     }
 }

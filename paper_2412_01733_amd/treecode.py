@@ -10,7 +10,10 @@ runs in the library's HIP kernels.  Functions here mirror the C ABI names:
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import threading
+import weakref
 
 import torch
 
@@ -19,6 +22,44 @@ from ._lib import check
 
 _WALKS = {"f32c": _lib.TC_WALK_F32C, "f64": _lib.TC_WALK_F64}
 _DT = {torch.float32: _lib.TC_F32, torch.float64: _lib.TC_F64}
+
+
+# torch's caching allocator serves every buffer the library owns (tc_set_allocator).
+# A block is handed back to the pool of the stream it was allocated on, so a free
+# is ordered after the work already enqueued on that stream: no device sync.
+_alloc_lock = threading.Lock()
+_alloc_cbs = None
+_live_trees = weakref.WeakSet()
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=None, stream=int(stream or 0))
+    except Exception:  # out of memory or no device: the library reports TC_ERR_NOMEM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+def _ensure_allocator(lib):
+    global _alloc_cbs
+    with _alloc_lock:
+        if _alloc_cbs is None:
+            cbs = (_lib.ALLOC_FN(_torch_alloc), _lib.FREE_FN(_torch_free))
+            check(lib.tc_set_allocator(cbs[0], cbs[1], None))
+            _alloc_cbs = cbs  # the C side keeps the pointers: keep the thunks alive
+
+
+@atexit.register
+def _free_live_trees():
+    # release handles while torch's allocator is still up
+    for t in list(_live_trees):
+        t.free()
 
 
 def _stream_ptr(device):
@@ -30,6 +71,8 @@ def _ptr(t):
 
 
 def _check_particles(pos, mass):
+    """Type, device and shape checks of (pos [n,3], mass [n]); returns the
+    tensors unchanged (callers decide whether a contiguous copy is allowed)."""
     if not (isinstance(pos, torch.Tensor) and isinstance(mass, torch.Tensor)):
         raise TypeError("pos and mass must be torch tensors")
     if pos.device.type != "cuda" or mass.device != pos.device:
@@ -38,7 +81,34 @@ def _check_particles(pos, mass):
         raise TypeError("pos and mass must both be float32 or both float64")
     if pos.dim() != 2 or pos.shape[1] != 3 or mass.dim() != 1 or mass.shape[0] != pos.shape[0]:
         raise ValueError("pos must be [n,3] and mass [n]")
-    return pos.contiguous(), mass.contiguous()
+    return pos, mass
+
+
+def _check_buffer(name, t, shape, dtype, device, required=True):
+    """A caller-supplied buffer the library reads or writes in place: it must
+    have exactly this shape, dtype and device and be contiguous, otherwise the
+    kernels would touch memory outside it.  Raises before any launch."""
+    if t is None:
+        if required:
+            raise ValueError("%s is required" % name)
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.device != device:
+        raise ValueError("%s must live on %s, got %s" % (name, device, t.device))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _walk_dtype(walk):
+    if walk not in _WALKS:
+        raise ValueError("walk must be one of %s" % sorted(_WALKS))
+    return torch.float32 if walk == "f32c" else torch.float64
 
 
 class Tree:
@@ -46,22 +116,29 @@ class Tree:
 
     def __init__(self):
         self._lib = _lib.load()
+        _ensure_allocator(self._lib)
         self._h = ctypes.c_void_p(None)
+        _live_trees.add(self)
         self.n = 0
         self.device = None
         self._walk = None
         self._timing = None
         self._timing_applied = False
 
-    def __del__(self):
+    def free(self):
+        """Release the handle (waits for its enqueued work)."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             self._lib.tc_tree_free(h)
             self._h = ctypes.c_void_p(None)
 
+    def __del__(self):
+        self.free()
+
     # -- C ABI calls ---------------------------------------------------------
     def build(self, pos, mass):
         pos, mass = _check_particles(pos, mass)
+        pos, mass = pos.contiguous(), mass.contiguous()  # read only: a copy is harmless
         self.device = pos.device
         self.n = pos.shape[0]
         with torch.cuda.device(pos.device):
@@ -81,13 +158,15 @@ class Tree:
     def forces(self, theta, eps, G=1.0, walk="f32c", count=False, store_lists=False, potential=True,
                out=None):
         """(acc [n,3], pot [n] or None) in caller order; float32 for f32c, float64 for f64."""
+        dt = _walk_dtype(walk)
         mode = _WALKS[walk]
-        dt = torch.float32 if walk == "f32c" else torch.float64
         if out is None:
             acc = torch.empty((self.n, 3), dtype=dt, device=self.device)
             pot = torch.empty((self.n,), dtype=dt, device=self.device) if potential else None
         else:
             acc, pot = out
+            _check_buffer("acc", acc, (self.n, 3), dt, self.device)
+            _check_buffer("pot", pot, (self.n,), dt, self.device, required=False)
         flags = (_lib.TC_COUNT if count else 0) | (_lib.TC_STORE_LISTS if store_lists else 0)
         with torch.cuda.device(self.device):
             check(self._lib.tc_forces(self._h, float(theta), float(eps), float(G), mode, flags,
@@ -96,7 +175,15 @@ class Tree:
         return acc, pot
 
     def backward(self, g_acc, g_pot=None, need_pos=True, need_mass=True):
-        dt = torch.float32 if self._walk == "f32c" else torch.float64
+        if self._walk is None:
+            raise RuntimeError("backward needs a forces() call on this tree first")
+        dt = _walk_dtype(self._walk)
+        # read only: converted copies are allowed, but shape and device must match
+        for name, g, shape in (("g_acc", g_acc, (self.n, 3)), ("g_pot", g_pot, (self.n,))):
+            if g is None:
+                continue
+            if not isinstance(g, torch.Tensor) or tuple(g.shape) != shape or g.device != self.device:
+                raise ValueError("%s must be a tensor of shape %s on %s" % (name, shape, self.device))
         g_acc = g_acc.to(dt).contiguous()
         g_pot = g_pot.to(dt).contiguous() if g_pot is not None else None
         g_pos = torch.empty((self.n, 3), dtype=dt, device=self.device) if need_pos else None
@@ -124,7 +211,10 @@ class Tree:
                     lane_visits=int(s.lane_visits), momentum=list(s.momentum),
                     sum_m_abs_a=s.sum_m_abs_a, kinetic=s.kinetic, potential=s.potential,
                     lin_momentum=list(s.lin_momentum), ang_momentum=list(s.ang_momentum),
-                    stage_ms=list(s.stage_ms), lists_stored=bool(s.lists_stored))
+                    stage_ms=list(s.stage_ms), lists_stored=bool(s.lists_stored),
+                    max_stack=int(s.max_stack), group_pops=int(s.group_pops),
+                    visits_no_accept=int(s.visits_no_accept), visits_all_accept=int(s.visits_all_accept),
+                    visits_box_open=int(s.visits_box_open), visits_box_accept=int(s.visits_box_accept))
 
     def export(self, moments=True):
         st = self.stats()
@@ -200,14 +290,15 @@ def leapfrog_step(pos, vel, mass, acc, tau, theta, eps, G=1.0, walk="f32c", pot=
     pos, vel, mass: [n,3], [n,3], [n] of one float dtype; acc (and pot) are of
     the walk's precision and hold a^n on entry, a^{n+1} on exit.  Returns the
     tree handle (reuse it for the next step)."""
+    # pos, vel, acc and pot are updated in place: they are checked as given, never copied
     pos, mass = _check_particles(pos, mass)
-    if not (vel.is_contiguous() and pos.is_contiguous() and acc.is_contiguous()):
-        raise ValueError("pos, vel and acc must be contiguous (they are updated in place)")
-    if vel.shape != pos.shape or vel.dtype != pos.dtype or vel.device != pos.device:
-        raise ValueError("vel must match pos")
-    adt = torch.float32 if walk == "f32c" else torch.float64
-    if acc.dtype != adt or acc.shape != pos.shape:
-        raise ValueError("acc must be [n,3] of the walk precision")
+    n = pos.shape[0]
+    _check_buffer("pos", pos, (n, 3), pos.dtype, pos.device)
+    mass = mass.contiguous()  # read only
+    _check_buffer("vel", vel, (n, 3), pos.dtype, pos.device)
+    adt = _walk_dtype(walk)
+    _check_buffer("acc", acc, (n, 3), adt, pos.device)
+    _check_buffer("pot", pot, (n,), adt, pos.device, required=False)
     t = tree if tree is not None else Tree()
     t.device = pos.device
     t.n = pos.shape[0]

@@ -115,6 +115,21 @@ def disc_galaxy(n_disc: int, n_halo: int, seed: int, dtype=np.float32,
     return pos.astype(dtype), vel.astype(dtype), mass.astype(dtype)
 
 
+def clumps(n_per: int, centres, radius: float, seed: int, dtype=np.float64):
+    """Compact Plummer clumps (scale ``radius``, truncated at 10 radius) of
+    n_per particles each, centred at ``centres`` [k,3], masses 1/(k n_per):
+    a multi-scale set whose clumps lie far apart relative to their size.
+    The clumps are listed one after another (caller order)."""
+    centres = np.asarray(centres, np.float64)
+    parts = []
+    for c, ctr in enumerate(centres):
+        p, _ = plummer(n_per, seed + c)
+        parts.append(ctr + radius * p)
+    pos = np.concatenate(parts)
+    m = np.full(len(pos), 1.0 / len(pos))
+    return pos.astype(dtype), m.astype(dtype)
+
+
 def target_sample(n: int, k: int, seed: int):
     """k distinct caller indices out of n, sorted (seeded)."""
     g = rng(seed)
