@@ -148,6 +148,27 @@ tc_status tc_leapfrog_step(tc_tree** tree, void* pos, void* vel, const void* mas
                            void* acc, void* pot, int64_t n, tc_dtype dtype, double tau,
                            double theta, double eps, double G, tc_walk mode, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * sequence tc_build + tc_moments + tc_forces (flags 0) in one call that
+ * allocates nothing.  No handle: every buffer of the build, the moments and
+ * the walk comes from one static device array of 128 MiB per GPU (held until
+ * the process ends, addressed through hipGetSymbolAddress), and the host side
+ * uses static storage.  Results are bitwise those of the three calls above
+ * (the same kernels in the same order).
+ *   pos [n,3], mass [n] of `dtype`; acc [n,3] (required) and pot [n] (may be
+ *   NULL) of the walk precision, caller order.  0 <= n <= 2^18.
+ * Blocks once (node count read back), as tc_build.  Every call on a GPU
+ * shares that GPU's array, which keeps the last call's contents; calls that
+ * overlap on one GPU (from several host threads or on several streams) race
+ * and must be serialised by the caller.
+ * Errors: as tc_build and tc_forces; TC_ERR_INVALID for n > 2^18, before any
+ * launch; TC_ERR_OVERFLOW when the particles' octree needs more than the
+ * static array (too many nodes), reported before any node kernel runs and
+ * before anything is written to acc or pot. */
+tc_status tc_forces_noalloc(const void* pos, const void* mass, int64_t n, tc_dtype dtype, double theta,
+                            double eps, double G, tc_walk mode, void* acc, void* pot, void* stream);
+
 /* Sizes, geometry, diagnostics and per-stage timings of a handle. */
 typedef struct {
     int64_t n;               /* particles */

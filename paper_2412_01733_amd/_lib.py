@@ -20,7 +20,7 @@ TC_COUNT, TC_STORE_LISTS = 1, 2
 
 # Every exported symbol of the C ABI, as declared in include/treecode.h.
 EXPORTS = ("tc_set_allocator", "tc_build", "tc_moments", "tc_forces", "tc_forces_backward",
-           "tc_leapfrog_step", "tc_tree_stats", "tc_tree_set_timing", "tc_tree_export",
+           "tc_forces_noalloc", "tc_leapfrog_step", "tc_tree_stats", "tc_tree_set_timing", "tc_tree_export",
            "tc_interaction_counts", "tc_tree_target_order", "tc_tree_free", "tc_last_error", "tc_version")
 
 
@@ -89,6 +89,8 @@ def load():
     L.tc_forces.restype = st
     L.tc_forces_backward.argtypes = [P, P, P, P, P, P]
     L.tc_forces_backward.restype = st
+    L.tc_forces_noalloc.argtypes = [P, P, I64, I, D, D, D, I, P, P, P]
+    L.tc_forces_noalloc.restype = st
     L.tc_leapfrog_step.argtypes = [ctypes.POINTER(P), P, P, P, P, P, I64, I, D, D, D, D, I, P]
     L.tc_leapfrog_step.restype = st
     L.tc_tree_stats.argtypes = [P, ctypes.POINTER(TcStats), P]

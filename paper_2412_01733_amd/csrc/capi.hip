@@ -109,6 +109,7 @@ struct tc_tree {
     double f_theta = 0.0, f_eps = 0.0, f_G = 1.0;  // parameters of the last tc_forces
     Geom geom_host{};
 
+    bool exact = false;  // size buffers exactly (the fixed scratch of tc_forces_noalloc), no growth slack
     bool timing = false;
     hipEvent_t ev[2 * kNumStages] = {};
     bool ev_used[kNumStages] = {};
@@ -125,7 +126,7 @@ tc_status ensure(tc_tree* t, Buf& b, size_t bytes, hipStream_t s)
     if (b.p) t->freef(b.p, s, t->actx);
     b.p = nullptr;
     b.bytes = 0;
-    size_t want = bytes + bytes / 4;
+    size_t want = t->exact ? bytes : bytes + bytes / 4;
     want = (want + 255) & ~(size_t)255;
     void* p = t->alloc(want, s, t->actx);
     if (!p) return fail(TC_ERR_NOMEM, "allocation of %zu bytes failed", want);
@@ -191,24 +192,10 @@ tc_status current_device(int* dev)
     return TC_OK;
 }
 
-tc_status create_tree(tc_tree** out, hipStream_t s)
+// The handle's small device block: root cube, diagnostics, counters, status.
+tc_status carve_small(tc_tree* t, hipStream_t s)
 {
-    int dev;
-    TC_TRY(current_device(&dev));
-    tc_tree* t = new tc_tree();
-    t->device = dev;
-    {
-        std::lock_guard<std::mutex> lk(g_alloc_mu);
-        t->alloc = g_alloc ? g_alloc : default_alloc;
-        t->freef = g_free ? g_free : default_free;
-        t->actx = g_alloc ? g_actx : nullptr;
-    }
-    size_t small = 1024;
-    tc_status st = ensure(t, t->small, small, s);
-    if (st != TC_OK) {
-        delete t;
-        return st;
-    }
+    TC_TRY(ensure(t, t->small, 1024, s));
     char* p = (char*)t->small.p;
     t->geom = (Geom*)p;
     p += (sizeof(Geom) + 15) & ~(size_t)15;
@@ -223,6 +210,26 @@ tc_status create_tree(tc_tree** out, hipStream_t s)
     t->level_hist = (uint32_t*)p;
     p += 4 * (kLevels + 2);
     t->status = (uint32_t*)p;
+    return TC_OK;
+}
+
+tc_status create_tree(tc_tree** out, hipStream_t s)
+{
+    int dev;
+    TC_TRY(current_device(&dev));
+    tc_tree* t = new tc_tree();
+    t->device = dev;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        t->alloc = g_alloc ? g_alloc : default_alloc;
+        t->freef = g_free ? g_free : default_free;
+        t->actx = g_alloc ? g_actx : nullptr;
+    }
+    tc_status st = carve_small(t, s);
+    if (st != TC_OK) {
+        delete t;
+        return st;
+    }
     if (hipHostMalloc((void**)&t->host, sizeof(HostMirror), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         release(t, t->small);
@@ -543,6 +550,64 @@ tc_status leapfrog_impl(tc_tree* t, void* pos, void* vel, const void* mass, void
 }
 
 
+// ---------------------------------------------------------------------------
+// tc_forces_noalloc: every buffer of the build, the moments and the walk comes
+// from one fixed device array per GPU, handed out by a bump allocator; the
+// host side uses a per-device handle and host mirror held in static storage.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = 128ull << 20;  // 128 MiB per GPU
+constexpr int64_t kNoAllocMaxN = 1 << 18;
+constexpr int kNoAllocMaxDevices = 64;
+
+}  // namespace
+
+// The scratch array.  In host code its name is only a stand-in: the device
+// address comes from hipGetSymbolAddress, once per device (each GPU holds its
+// own copy of the array, at its own address, until the process ends).
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+struct Bump {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+
+void* bump_alloc(size_t bytes, void*, void* ctx)
+{
+    Bump* b = (Bump*)ctx;
+    const size_t off = (b->used + 255) & ~(size_t)255;
+    if (off > b->cap || bytes > b->cap - off) return nullptr;
+    b->used = off + bytes;
+    return b->base + off;
+}
+
+void bump_free(void*, void*, void*) {}
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocMaxDevices] = {};  // device address of `scratch` on each device
+tc_tree g_noalloc_tree[kNoAllocMaxDevices];
+HostMirror g_noalloc_host[kNoAllocMaxDevices];
+Bump g_noalloc_bump[kNoAllocMaxDevices];
+
+tc_status noalloc_scratch(int dev, char** base)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(TC_ERR_DEVICE, "tc_forces_noalloc: hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        }
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *base = (char*)g_noalloc_ptr[dev];
+    return TC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -608,6 +673,50 @@ tc_status tc_forces_backward(tc_tree* t, const void* g_acc, const void* g_pot, v
     if (t->n > 0 && !g_acc) return fail(TC_ERR_INVALID, "tc_forces_backward: g_acc must be non-NULL");
     TC_TRY(check_device(t));
     return mark_done(t, (hipStream_t)stream, backward_impl(t, g_acc, g_pot, g_pos, g_mass, (hipStream_t)stream));
+}
+
+tc_status tc_forces_noalloc(const void* pos, const void* mass, int64_t n, tc_dtype dtype, double theta, double eps,
+                            double G, tc_walk mode, void* acc, void* pot, void* stream)
+{
+    g_err.clear();
+    if (n < 0 || n > kNoAllocMaxN)
+        return fail(TC_ERR_INVALID, "tc_forces_noalloc: n = %lld outside [0, %lld], the size its static scratch serves",
+                    (long long)n, (long long)kNoAllocMaxN);
+    if (dtype != TC_F32 && dtype != TC_F64) return fail(TC_ERR_INVALID, "tc_forces_noalloc: bad dtype %d", (int)dtype);
+    if (n > 0 && (!pos || !mass || !acc))
+        return fail(TC_ERR_INVALID, "tc_forces_noalloc: pos, mass and acc must be non-NULL");
+    if (!is_finite(theta) || theta < 0.0) return fail(TC_ERR_INVALID, "tc_forces_noalloc: theta must be finite and >= 0");
+    if (!is_finite(eps) || eps < 0.0) return fail(TC_ERR_INVALID, "tc_forces_noalloc: eps must be finite and >= 0");
+    if (!is_finite(G)) return fail(TC_ERR_INVALID, "tc_forces_noalloc: G must be finite");
+    if (mode != TC_WALK_F32C && mode != TC_WALK_F64) return fail(TC_ERR_INVALID, "tc_forces_noalloc: bad walk mode");
+    int dev;
+    TC_TRY(current_device(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(TC_ERR_DEVICE, "tc_forces_noalloc: device %d not served", dev);
+    char* base = nullptr;
+    TC_TRY(noalloc_scratch(dev, &base));
+    hipStream_t s = (hipStream_t)stream;
+    // a fresh handle over the scratch; the status of the previous call's walk is
+    // still reported at this call's synchronisation
+    tc_tree* t = &g_noalloc_tree[dev];
+    const bool status_pending = t->walk_status_pending;
+    *t = tc_tree{};
+    Bump* b = &g_noalloc_bump[dev];
+    *b = Bump{base, kNoAllocScratchBytes, 0};
+    t->device = dev;
+    t->alloc = bump_alloc;
+    t->freef = bump_free;
+    t->actx = b;
+    t->exact = true;
+    t->host = &g_noalloc_host[dev];
+    t->walk_status_pending = status_pending;
+    tc_status st = carve_small(t, s);
+    if (st == TC_OK) st = build_impl(t, pos, mass, n, dtype, s);
+    if (st == TC_OK) st = moments_impl(t, s);
+    if (st == TC_OK) st = forces_impl(t, theta, eps, G, mode, 0u, acc, pot, s);
+    if (st == TC_ERR_NOMEM)
+        return fail(TC_ERR_OVERFLOW, "tc_forces_noalloc: n = %lld particles with %lld octree nodes need more than the "
+                    "%zu-byte static scratch", (long long)n, (long long)t->nn, kNoAllocScratchBytes);
+    return st;
 }
 
 tc_status tc_leapfrog_step(tc_tree** tree, void* pos, void* vel, const void* mass, void* acc, void* pot,
