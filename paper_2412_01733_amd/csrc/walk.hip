@@ -39,19 +39,26 @@ namespace {
 
 constexpr int kWalkWaves = 4;
 constexpr int kWalkThreads = 64 * kWalkWaves;
-// Pending groups never exceed 7 per level for the group levels 2..20 plus 8
-// at the deepest (<= 141); a push beyond the stack is refused and flagged.
-constexpr int kStack = 160;
-// Group partial sums are folded into the compensated totals every few groups.
-constexpr int kFlushEvery = 4;
+// A step of the walk takes up to kBatchGroups sibling groups off the stack and
+// stages all their children at once, 8 lanes per group.
+constexpr int kBatchGroups = 4;
+constexpr int kBatchGroupsF64 = 3;  // the FP64 walk's larger records: 8 waves per SIMD still fit the LDS
+// Stack bound.  Taking one group and pushing the groups of its opened
+// children (at most 8) grows the stack by at most 7 per level below the
+// group, so a depth-first run that starts at height S never exceeds
+// S + 7 * 20 + 1 (groups lie at levels 1..21).  Several groups are taken
+// together only while sp + 7 * kBatchGroups <= kStackBatch, which leaves any
+// batch at height <= kStackBatch; single-group steps from there stay below
+// kStackBatch + 141 <= kStack.  A push beyond the stack therefore cannot
+// happen; it would be refused and flagged (status bit 0).
+constexpr int kStackDfs = 7 * 20 + 1;
+constexpr int kStack = 256;
+constexpr int kStackBatch = kStack - kStackDfs - 7;
 // Stored-list records are staged in LDS and written out this many at a time.
 constexpr uint32_t kListBuf = 32;
 // The adjoint replays stored records this many at a time.
 constexpr uint32_t kReplayChunk = 32;
 
-struct StackEntry {
-    uint32_t gs, nc, mlo, mhi;
-};
 
 // What a child needs on the hot path, staged once per group in LDS.
 struct __align__(16) Hot32 {
@@ -82,6 +89,13 @@ __device__ inline void wave_sync()
 
 __device__ inline uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uni_r(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ inline double uni_r(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b), hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
 
 // 1/sqrt(x) in FP64: with the hardware estimate y (relative error below
 // 2^-24, measured) and r = 1 - x y^2, the exact value is y (1 - r)^(-1/2);
@@ -207,13 +221,21 @@ __global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu((F
 void k_walk(WalkArgs a)
 {
     static_assert(!(ADJ && (COUNT || STORE)), "the adjoint walk neither counts nor stores");
+    // the straight run over decided accepts: the forward walks (the adjoint and
+    // the storing walk act per node with wave-wide steps, and take every child
+    // through the general path)
+    constexpr bool FAST = !ADJ && !STORE;
     using R = typename std::conditional<F64, double, float>::type;
     using Hot = typename std::conditional<F64, Hot64, Hot32>::type;
-    __shared__ StackEntry stk[kWalkWaves][kStack];
-    __shared__ Hot stg[kWalkWaves][8];
-    // opening thresholds by meta_tau_index: tau0 4^-l for level l, -1 for a one-particle leaf
-    __shared__ R taut[kWalkWaves][64];
-    __shared__ uint32_t stg_meta[kWalkWaves][8];
+    // the stack of pending sibling groups: first node, child count, lanes that opened the parent
+    __shared__ uint32_t stk_gs[kWalkWaves][kStack];
+    __shared__ uint8_t stk_nc[kWalkWaves][kStack];
+    __shared__ uint64_t stk_m[kWalkWaves][kStack];
+    // staged children of the groups of one step: slot 8 j + k holds child k of group j
+    constexpr int kGroups = F64 ? kBatchGroupsF64 : kBatchGroups;
+    __shared__ Hot stg[kWalkWaves][8 * kGroups];
+    __shared__ uint32_t stg_meta[kWalkWaves][8 * kGroups];
+    __shared__ uint4 popped[kWalkWaves][kGroups];  // the step's groups: first node, count, mask
     // adjoint: per staged child, the 4 row partials of (dL/dX, dL/dM)
     // adjoint, source side: FP64 walk - per pending node, the 4 row partials of
     // (dL/dX, dL/dM); FP32 walk - per pending node, every lane's 4 values
@@ -234,7 +256,6 @@ void k_walk(WalkArgs a)
     const int64_t wave_id = (int64_t)blockIdx.x * kWalkWaves + w;
     const int64_t base = wave_id * 64;
     if (base >= a.n) return;  // whole wave; no block barrier follows
-    taut[w][lane] = lane < 32 ? (R)ldexp(tau0, -2 * (int)lane) : (R)-1;  // exact power-of-two scaling
     // this lane's target (sorted position) and the range of sorted positions the
     // wavefront's targets span (a superset of them: only a node overlapping it
     // can hold one of the targets)
@@ -282,39 +303,46 @@ void k_walk(WalkArgs a)
     uint64_t vis_nodes = 0, vis_lanes = 0, vis_groups = 0, vis_noacc = 0, vis_allacc = 0, vis_boxopen = 0,
              vis_boxacc = 0;
     int max_sp = 0;
-    // counting walk: bounding box of the wavefront's targets (anchor-relative) for the box test
-    R bnx = 0, bny = 0, bnz = 0, bxx = 0, bxy = 0, bxz = 0;
-    if constexpr (COUNT) {
-        bnx = valid ? px : (R)INFINITY; bny = valid ? py : (R)INFINITY; bnz = valid ? pz : (R)INFINITY;
-        bxx = valid ? px : (R)-INFINITY; bxy = valid ? py : (R)-INFINITY; bxz = valid ? pz : (R)-INFINITY;
+    // The bounding box [bn, bx] of the wavefront's targets (the same offsets the
+    // lanes use).  Rounding is monotone, so for a node at X every lane's
+    // |fl(X - p)| lies between the box's fl-gap and its fl-far side per axis, and
+    // the lane's d^2 (the same fused operations) between the box's two d^2:
+    // a node whose near d^2 exceeds the threshold is far from every lane, one
+    // whose far d^2 does not is near to every lane, with no margin needed.
+    R bnx = valid ? px : (R)INFINITY, bny = valid ? py : (R)INFINITY, bnz = valid ? pz : (R)INFINITY;
+    R bxx = valid ? px : (R)-INFINITY, bxy = valid ? py : (R)-INFINITY, bxz = valid ? pz : (R)-INFINITY;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            bnx = fmin(bnx, __shfl_xor(bnx, o, 64)); bny = fmin(bny, __shfl_xor(bny, o, 64));
-            bnz = fmin(bnz, __shfl_xor(bnz, o, 64)); bxx = fmax(bxx, __shfl_xor(bxx, o, 64));
-            bxy = fmax(bxy, __shfl_xor(bxy, o, 64)); bxz = fmax(bxz, __shfl_xor(bxz, o, 64));
-        }
+    for (int o = 32; o > 0; o >>= 1) {
+        bnx = fmin(bnx, __shfl_xor(bnx, o, 64)); bny = fmin(bny, __shfl_xor(bny, o, 64));
+        bnz = fmin(bnz, __shfl_xor(bnz, o, 64)); bxx = fmax(bxx, __shfl_xor(bxx, o, 64));
+        bxy = fmax(bxy, __shfl_xor(bxy, o, 64)); bxz = fmax(bxz, __shfl_xor(bxz, o, 64));
     }
+    bnx = uni_r(bnx); bny = uni_r(bny); bnz = uni_r(bnz);
+    bxx = uni_r(bxx); bxy = uni_r(bxy); bxz = uni_r(bxz);
 
     int sp = 0;
-    bool stack_over = false;
-    int since_flush = 0;
+    bool stack_over = false, corrupt = false;
 
     // The terms of an opened leaf's particles f .. f+cnt-1 for the lanes in om,
     // the target itself excluded.
+    // Particles that share a level-21 cell can sit far closer together than
+    // FP32 offsets from the wave's anchor resolve, so their separation is
+    // formed in FP64 from this lane's own position (read again here: the leaf
+    // is rare, and keeping it in registers would cost the walk occupancy).
     auto leaf_terms = [&](const uint32_t f, const uint32_t cnt, const uint64_t om) {
         const bool lane_open = (om >> lane) & 1ull;
+        double mx = xs, my = ys, mz = zs;
+        if constexpr (!F64) {
+            const Particle me = a.sp[su];
+            mx = me.x; my = me.y; mz = me.z;
+        }
         for (uint32_t j = f; j < f + cnt; ++j) {
             const Particle pj = a.sp[j];
             const double xj = pj.x, yj = pj.y, zj = pj.z;
             const R mj = (R)pj.m;
             R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
             if (lane_open && j != su) {
-                R ex, ey, ez;
-                if constexpr (F64) {
-                    ex = xj - xs; ey = yj - ys; ez = zj - zs;
-                } else {
-                    ex = (float)(xj - Ax) - px; ey = (float)(yj - Ay) - py; ez = (float)(zj - Az) - pz;
-                }
+                const R ex = (R)(xj - mx), ey = (R)(yj - my), ez = (R)(zj - mz);
                 const R q = fma(ex, ex, fma(ey, ey, ez * ez)) + eps2;
                 if constexpr (!ADJ) {
                     const R ri = rsqrt_any(q);
@@ -477,22 +505,36 @@ void k_walk(WalkArgs a)
         const uint32_t rmeta = uni(a.nodes[0].meta);
         const uint32_t rchild = uni(a.nodes[0].child);
         if (!meta_leaf(rmeta)) {
-            if (lane == 0) stk[w][0] = StackEntry{rchild, meta_nchild(rmeta), (uint32_t)vmask, (uint32_t)(vmask >> 32)};
+            if (lane == 0) {
+                stk_gs[w][0] = rchild;
+                stk_nc[w][0] = (uint8_t)meta_nchild(rmeta);
+                stk_m[w][0] = vmask;
+            }
             sp = 1;
         }
     }
     wave_sync();
 
     while (sp > 0) {
-        sp = uni(sp - 1);
-        const StackEntry e = stk[w][sp];
-        const uint32_t gs = uni(e.gs);
-        const uint32_t nc = min(uni(e.nc), 8u);
-        const uint64_t mask = ((uint64_t)uni(e.mhi) << 32) | uni(e.mlo);
+        // take ng groups off the top; lanes 8 j .. 8 j + 7 stage the children of group j
+        const int ng = sp <= kStackBatch - 7 * kGroups ? min(sp, kGroups) : 1;
+        const int gj = (int)(lane >> 3), gk = (int)(lane & 7);
+        uint32_t e_gs = 0, e_nc = 0;
+        if (gj < ng) {
+            const int slot = sp - 1 - gj;
+            e_gs = stk_gs[w][slot];
+            e_nc = stk_nc[w][slot];
+            if (gk == 0) {
+                const uint64_t e_m = stk_m[w][slot];
+                popped[w][gj] = make_uint4(e_gs, e_nc, (uint32_t)e_m, (uint32_t)(e_m >> 32));
+            }
+        }
+        sp = uni(sp - ng);
         bool ovl = false;  // may the child contain one of this wave's targets?
-        const WalkNode* grp = a.nodes + gs;  // uniform base of the group
-        if (lane < nc) {
-            const WalkNode nd = grp[lane];
+        bool bad = false, all_far = false, all_near = false;
+        if (gj < ng && gk < (int)e_nc) {
+            bad = e_nc > 8u;
+            const WalkNode nd = a.nodes[e_gs + (uint32_t)gk];
             ovl = nd.first < wave_end && nd.first + nd.count > wave_lo;
             Hot h;
             if constexpr (F64) {
@@ -501,53 +543,56 @@ void k_walk(WalkArgs a)
                 h.x = (float)(nd.x - Ax); h.y = (float)(nd.y - Ay); h.z = (float)(nd.z - Az);
                 h.m = (float)nd.m;
             }
-            h.tau = taut[w][meta_tau_index(nd.meta)];
+            // opening threshold tau0 4^-l (an exact power-of-two scaling); a
+            // one-particle leaf is always taken (-1)
+            h.tau = meta_single(nd.meta) ? (R)-1 : (R)ldexp(tau0, -2 * (int)meta_level(nd.meta));
             h.first = nd.first;
             h.count = nd.count;
             h.child = nd.child;
             stg[w][lane] = h;
             stg_meta[w][lane] = nd.meta;
+            // the box test (see bn, bx): decided for every target of the wavefront
+            const R gx = fmax(fmax(bnx - h.x, h.x - bxx), (R)0), fx = fmax(fabs(h.x - bnx), fabs(h.x - bxx));
+            const R gy = fmax(fmax(bny - h.y, h.y - bxy), (R)0), fy = fmax(fabs(h.y - bny), fabs(h.y - bxy));
+            const R gz = fmax(fmax(bnz - h.z, h.z - bxz), (R)0), fz = fmax(fabs(h.z - bnz), fabs(h.z - bxz));
+            all_far = !ovl && fma(gx, gx, fma(gy, gy, gz * gz)) > h.tau;
+            all_near = !(fma(fx, fx, fma(fy, fy, fz * fz)) > h.tau);
         }
         const uint64_t ovl_m = __ballot(ovl);
+        const uint64_t far_all = __ballot(all_far), near_all = __ballot(all_near);
+        if (__ballot(bad)) corrupt = true;
         wave_sync();
 
-        if constexpr (COUNT) {
-            vis_nodes += nc;
-            vis_lanes += (uint64_t)nc * (uint64_t)__popcll(mask);
-            vis_groups += 1;
-            max_sp = max(max_sp, sp + 1);
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if ((uint32_t)k >= nc) break;
-            const Hot h = stg[w][k];  // one broadcast read of the whole record
-            const R dx = h.x - px, dy = h.y - py, dz = h.z - pz;
-            const R d2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            // lane masks combined on the scalar unit: accepted = active, not containing, far enough
-            uint64_t in_m = 0;
-            if ((ovl_m >> k) & 1ull) in_m = __ballot((su - h.first) < h.count);
-            const uint64_t far_m = __ballot(d2 > h.tau);
-            const uint64_t am = mask & far_m & ~in_m;
+        for (int j = 0; j < ng; ++j) {
+            const uint4 e = popped[w][j];
+            const uint32_t gs = uni(e.x);
+            const uint32_t nc = min(uni(e.y), 8u);
+            const uint64_t mask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
             if constexpr (COUNT) {
-                vis_noacc += am == 0;
-                vis_allacc += am == mask;
-                // box test: every target of the wave lies in [bn, bx]; with a relative
-                // margin for the rounding of both distances, a node farther than s/theta
-                // from the whole box is accepted by every lane, one nearer from all of it
-                // is opened by every lane
-                const R ex = fmax(fmax(bnx - h.x, h.x - bxx), (R)0);
-                const R ey = fmax(fmax(bny - h.y, h.y - bxy), (R)0);
-                const R ez = fmax(fmax(bnz - h.z, h.z - bxz), (R)0);
-                const R fx = fmax(fabs(h.x - bnx), fabs(h.x - bxx));
-                const R fy = fmax(fabs(h.y - bny), fabs(h.y - bxy));
-                const R fz = fmax(fabs(h.z - bnz), fabs(h.z - bxz));
-                const R dmin2 = ex * ex + ey * ey + ez * ez, dmax2 = fx * fx + fy * fy + fz * fz;
-                const R marg = (R)1 + (R)0x1p-18;
-                vis_boxopen += h.tau >= (R)0 && dmax2 * marg < h.tau;
-                vis_boxacc += !((ovl_m >> k) & 1ull) && (h.tau < (R)0 || dmin2 > h.tau * marg);
+                vis_nodes += nc;
+                vis_lanes += (uint64_t)nc * (uint64_t)__popcll(mask);
+                vis_groups += 1;
             }
-            if constexpr (!ADJ) {
-                if (__builtin_amdgcn_inverse_ballot_w64(am)) {
+            const uint32_t all = (1u << nc) - 1u;
+            // decided accepted by every target, and not holding any (the forward
+            // walks take these in one straight run with the active lanes enabled)
+            uint32_t fast = FAST ? (uint32_t)(far_all >> (8 * j)) & all : 0u;
+            // decided opened by every active target
+            uint32_t opened = (uint32_t)(near_all >> (8 * j)) & all & ~fast;
+            uint32_t slow = all & ~fast & ~opened;
+            if constexpr (COUNT) {
+                vis_allacc += __popc(fast);
+                vis_boxacc += __popc(fast);
+                vis_noacc += __popc(opened);
+                vis_boxopen += __popc(opened);
+            }
+            if (fast && __builtin_amdgcn_inverse_ballot_w64(mask)) {
+                do {
+                    const uint32_t k = __builtin_ctz(fast);
+                    fast &= fast - 1u;
+                    const Hot h = stg[w][8u * (uint32_t)j + k];
+                    const R dx = h.x - px, dy = h.y - py, dz = h.z - pz;
+                    const R d2 = fma(dx, dx, fma(dy, dy, dz * dz));
                     const R ri = rsqrt_any(d2 + eps2);
                     const R mr = h.m * ri;
                     const R mr3 = mr * (ri * ri);
@@ -556,52 +601,89 @@ void k_walk(WalkArgs a)
                     bz = fma(mr3, dz, bz);
                     bp -= mr;
                     if constexpr (COUNT) ++nint;
-                }
-                if constexpr (STORE) {
-                    if (am) list_put(gs + k, 0u, am);
-                }
-            } else {
-                if (am) {
-                    R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
-                    if (__builtin_amdgcn_inverse_ballot_w64(am)) {
-                        adj_term(dx, dy, dz, d2 + eps2, h.m, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
-                        bx -= sx0;
-                        by -= sy0;
-                        bz -= sz0;
-                    }
-                    src_put(gs + k, sx0, sy0, sz0, sm0);
-                }
+                } while (fast);
             }
-            const uint64_t om = mask & ~am;
-            if (om) {
-                const uint32_t meta = uni(stg_meta[w][k]);
+            // an opened child: its own group is pushed, or an opened leaf's particles
+            // are taken one by one, the target itself excluded (for a one-particle
+            // leaf only the lane holding that particle gets here, and it contributes nothing)
+            auto open_child = [&](const uint32_t slot, const uint32_t k, const uint64_t om) {
+                const uint32_t meta = uni(stg_meta[w][slot]);
                 if (!meta_leaf(meta)) {
-                    const uint32_t child = uni(h.child);
+                    const uint32_t child = uni(stg[w][slot].child);
                     if (sp < kStack) {
-                        if (lane == 0) stk[w][sp] = StackEntry{child, meta_nchild(meta), (uint32_t)om, (uint32_t)(om >> 32)};
+                        if (lane == 0) {
+                            stk_gs[w][sp] = child;
+                            stk_nc[w][sp] = (uint8_t)meta_nchild(meta);
+                            stk_m[w][sp] = om;
+                        }
                         sp = uni(sp + 1);
+                        if constexpr (COUNT) max_sp = max(max_sp, sp);
                     } else {
                         stack_over = true;
                     }
                 } else {
-                    // an opened leaf: its particles one by one, the target itself excluded
-                    // (for a one-particle leaf only the lane holding that particle gets here,
-                    // and it contributes nothing)
-                    const uint32_t f = uni(h.first), cnt = uni(h.count);
+                    const uint32_t f = uni(stg[w][slot].first), cnt = uni(stg[w][slot].count);
                     if (cnt > 1) {
                         leaf_terms(f, cnt, om);
                         if constexpr (STORE) list_put(gs + k, 1u, om);
                     }
                 }
+            };
+            while (opened) {
+                const uint32_t k = __builtin_ctz(opened);
+                opened &= opened - 1u;
+                open_child(8u * (uint32_t)j + k, k, mask);
+            }
+            while (slow) {
+                const uint32_t k = __builtin_ctz(slow);
+                slow &= slow - 1u;
+                const uint32_t slot = 8u * (uint32_t)j + k;
+                const Hot h = stg[w][slot];  // one broadcast read of the whole record
+                const R dx = h.x - px, dy = h.y - py, dz = h.z - pz;
+                const R d2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                // lane masks combined on the scalar unit: accepted = active, not containing, far enough
+                uint64_t in_m = 0;
+                if ((ovl_m >> slot) & 1ull) in_m = __ballot((su - h.first) < h.count);
+                const uint64_t far_m = __ballot(d2 > h.tau);
+                const uint64_t am = mask & far_m & ~in_m;
+                if constexpr (COUNT) {
+                    vis_noacc += am == 0;
+                    vis_allacc += am == mask;
+                }
+                if constexpr (!ADJ) {
+                    if (__builtin_amdgcn_inverse_ballot_w64(am)) {
+                        const R ri = rsqrt_any(d2 + eps2);
+                        const R mr = h.m * ri;
+                        const R mr3 = mr * (ri * ri);
+                        bx = fma(mr3, dx, bx);
+                        by = fma(mr3, dy, by);
+                        bz = fma(mr3, dz, bz);
+                        bp -= mr;
+                        if constexpr (COUNT) ++nint;
+                    }
+                    if constexpr (STORE) {
+                        if (am) list_put(gs + k, 0u, am);
+                    }
+                } else {
+                    if (am) {
+                        R sx0 = 0, sy0 = 0, sz0 = 0, sm0 = 0;
+                        if (__builtin_amdgcn_inverse_ballot_w64(am)) {
+                            adj_term(dx, dy, dz, d2 + eps2, h.m, gxl, gyl, gzl, hl, sx0, sy0, sz0, sm0);
+                            bx -= sx0;
+                            by -= sy0;
+                            bz -= sz0;
+                        }
+                        src_put(gs + k, sx0, sy0, sz0, sm0);
+                    }
+                }
+                const uint64_t om = mask & ~am;
+                if (om) open_child(slot, k, om);
             }
         }
-        wave_sync();
-        if (++since_flush == kFlushEvery || sp == 0) {
-            since_flush = 0;
-            fold();
-        }
+        wave_sync();  // the next step restages the slots and rereads the stack
+        fold();
     }
-    if (stack_over && lane == 0) atomicOr(a.status, 1u);
+    if (lane == 0 && (stack_over || corrupt)) atomicOr(a.status, (stack_over ? 1u : 0u) | (corrupt ? 2u : 0u));
     if constexpr (ADJ) src_flush();
     if constexpr (STORE) {
         list_flush();

@@ -46,13 +46,20 @@ def _torch_free(ptr, stream, ctx):
         pass
 
 
-def _ensure_allocator(lib):
+def _ensure_allocator(lib, force=False):
     global _alloc_cbs
     with _alloc_lock:
-        if _alloc_cbs is None:
-            cbs = (_lib.ALLOC_FN(_torch_alloc), _lib.FREE_FN(_torch_free))
+        if _alloc_cbs is None or force:
+            cbs = _alloc_cbs or (_lib.ALLOC_FN(_torch_alloc), _lib.FREE_FN(_torch_free))
             check(lib.tc_set_allocator(cbs[0], cbs[1], None))
             _alloc_cbs = cbs  # the C side keeps the pointers: keep the thunks alive
+
+
+def bind_torch_allocator():
+    """(Re)install torch's caching allocator for handles created from now on
+    (done automatically by the first Tree; needed again only after another
+    allocator was installed through tc_set_allocator)."""
+    _ensure_allocator(_lib.load(), force=True)
 
 
 @atexit.register

@@ -1,0 +1,118 @@
+"""The Python binding and the C ABI at their edges, on the GPU: caller
+buffers are checked before any launch (a wrong shape, dtype, layout or a
+strided view that would be updated through a copy raises and leaves the
+buffers untouched), the library's buffers come from torch's caching
+allocator, and the walk status is clean after every walk kind."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def _set(n=3000, seed=41, dtype=np.float32):
+    pos, m = workloads.plummer(n, seed, dtype=dtype)
+    return torch.from_numpy(pos).to(dev()), torch.from_numpy(m).to(dev())
+
+
+def test_leapfrog_refuses_a_strided_position_view():
+    """A position view that is not contiguous would be drifted through a
+    temporary copy, leaving the caller's positions unchanged: refused."""
+    import paper_2412_01733_amd as tc
+    p, m = _set()
+    n = p.shape[0]
+    state = torch.cat([p, torch.zeros_like(p)], dim=1)  # [n, 6]: positions are a strided view
+    pos_view = state[:, :3]
+    assert not pos_view.is_contiguous()
+    vel = torch.zeros_like(p)
+    acc = torch.zeros((n, 3), dtype=torch.float32, device=dev())
+    before = state.clone()
+    with pytest.raises(ValueError, match="pos must be contiguous"):
+        tc.leapfrog_step(pos_view, vel, m, acc, 1e-3, 0.5, 0.01)
+    torch.cuda.synchronize()
+    assert torch.equal(state, before) and bool((vel == 0).all()) and bool((acc == 0).all())
+
+
+@pytest.mark.parametrize("bad", ["dtype", "shape", "strided"])
+def test_forces_out_buffers_checked(bad):
+    import paper_2412_01733_amd as tc
+    p, m = _set()
+    n = p.shape[0]
+    t = tc.Tree().build(p, m).moments()
+    acc = torch.full((n, 3), 5.0, dtype=torch.float32, device=dev())
+    pot = torch.full((n,), 5.0, dtype=torch.float32, device=dev())
+    if bad == "dtype":  # an FP32 buffer handed to the FP64 walk
+        exc, kw = TypeError, dict(walk="f64", out=(acc, pot))
+    elif bad == "shape":
+        exc, kw = ValueError, dict(walk="f32c", out=(acc[: n - 1], pot))
+    else:
+        exc, kw = ValueError, dict(walk="f32c", out=(acc, torch.full((2 * n,), 5.0, device=dev())[::2]))
+    with pytest.raises(exc):
+        t.forces(0.5, 0.01, **kw)
+    torch.cuda.synchronize()
+    assert bool((acc == 5.0).all()) and bool((pot == 5.0).all())
+
+
+def test_leapfrog_buffers_checked():
+    import paper_2412_01733_amd as tc
+    p, m = _set()
+    n = p.shape[0]
+    vel = torch.zeros_like(p)
+    with pytest.raises(TypeError):  # FP64 acc for the FP32 walk
+        tc.leapfrog_step(p, vel, m, torch.zeros((n, 3), dtype=torch.float64, device=dev()), 1e-3, 0.5, 0.01)
+    with pytest.raises(ValueError):  # short potential
+        tc.leapfrog_step(p, vel, m, torch.zeros((n, 3), device=dev()), 1e-3, 0.5, 0.01,
+                         pot=torch.zeros(n - 1, device=dev()))
+
+
+def test_backward_gradient_shapes_checked():
+    import paper_2412_01733_amd as tc
+    p, m = _set()
+    n = p.shape[0]
+    t = tc.Tree().build(p, m).moments()
+    t.forces(0.5, 0.01)
+    with pytest.raises(ValueError):
+        t.backward(torch.ones((n - 1, 3), device=dev()))
+    with pytest.raises(ValueError):
+        t.backward(torch.ones((n, 3), device=dev()), torch.ones(n + 1, device=dev()))
+
+
+def test_buffers_come_from_torch_allocator():
+    import paper_2412_01733_amd as tc
+    tc.treecode.bind_torch_allocator()
+    p, m = _set(200_000, 42)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    t = tc.Tree().build(p, m).moments()
+    t.forces(0.5, 0.01)
+    torch.cuda.synchronize()
+    held = torch.cuda.memory_allocated() - before
+    # keys, sort buffers, particle records and the node arrays: well over 50 B per particle
+    assert held > 50 * 200_000, held
+    t.free()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - before < held
+
+
+@pytest.mark.parametrize("walk", ["f32c", "f64"])
+def test_walk_status_clean(walk):
+    """Forward, counted, storing and adjoint walks leave the status word clear
+    (tc_tree_stats would report an overflow or a corrupt tree otherwise), and
+    a rebuild on the handle reads it at its synchronisation."""
+    import paper_2412_01733_amd as tc
+    p, m = _set(20000, 43)
+    t = tc.Tree().build(p, m).moments()
+    for kw in (dict(), dict(count=True), dict(store_lists=True)):
+        acc, _ = t.forces(0.5, 0.01, walk=walk, **kw)
+        t.stats()  # raises TreecodeError on a non-zero status
+    t.backward(torch.ones_like(acc))
+    t.stats()
+    t.forces(0.5, 0.01, walk=walk)
+    t.build(p, m)  # checks the previous walk's status at its sync

@@ -6,8 +6,9 @@ times (one tc_build + tc_moments + tc_forces through the C ABI).
     oracle over all 1e7 particles and ~1.5e7 nodes; the walk's target order a
     permutation of all 1e7 targets;
   * accelerations and potentials at theta in {0.3, 0.5, 0.8}: on 4096 seeded
-    targets the oracle evaluates one by one, F32C median <= 1e-5 and
-    p99 <= 1e-4, F64 median <= 1e-13 and p99 <= 1e-11;
+    targets the oracle evaluates one by one, the bars of tests/bars.py
+    (F32C median <= 1e-5, p99 <= 1e-4, every count-matching target <= 1e-4;
+    F64 median <= 1e-13, p99 <= 1e-11, count-matching targets <= 1e-12);
   * interaction counts on the sample: F64 differs from the oracle on at most
     0.1% of targets, F32C on under 1% (distances within FP32 rounding of the
     opening threshold);
@@ -22,6 +23,7 @@ import pytest
 
 import oracle
 import workloads
+from bars import check_errors, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -73,17 +75,19 @@ def test_fullsize_sampled_forces(big, theta):
     ra, rp, rn = big["T"].forces(theta, EPS, targets=tg)
     sel = torch.from_numpy(tg).to(big["dev"])
     rp_ratio = {}
-    for walk, med, p99, flip_bar in (("f32c", 1e-5, 1e-4, 0.01), ("f64", 1e-13, 1e-11, 1e-3)):
+    for walk, flip_bar in (("f32c", 0.01), ("f64", 1e-3)):
         print("fullsize: theta=%g walk=%s" % (theta, walk), flush=True)
         acc, pot = tree.forces(theta, EPS, walk=walk, count=True)
         cnt = tree.interaction_counts()[sel].cpu().numpy().astype(np.int64)
         st = tree.stats()
         a = acc[sel].double().cpu().numpy()
         p = pot[sel].double().cpu().numpy()
-        e = np.linalg.norm(a - ra, axis=1) / np.linalg.norm(ra, axis=1)
-        ep = np.abs(p - rp) / np.abs(rp)
-        assert np.median(e) <= med and np.quantile(e, 0.99) <= p99, (walk, np.median(e), np.quantile(e, 0.99))
-        assert np.median(ep) <= med and np.quantile(ep, 0.99) <= p99, (walk, np.median(ep), np.quantile(ep, 0.99))
+        e = rel_err(a, ra)
+        ep = rel_err(p, rp)
+        same = cnt == rn
+        print("fullsize: max over count-matching targets %.3g (pot %.3g)" % (e[same].max(), ep[same].max()), flush=True)
+        check_errors(e, walk, same, "acc")
+        check_errors(ep, walk, same, "pot")
         assert np.mean(cnt != rn) <= flip_bar, (walk, np.mean(cnt != rn))
         rp_ratio[walk] = np.linalg.norm(st["momentum"]) / st["sum_m_abs_a"]
     assert abs(rp_ratio["f32c"] - rp_ratio["f64"]) <= 1e-6, rp_ratio
