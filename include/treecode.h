@@ -203,6 +203,11 @@ typedef struct {
     uint64_t visits_box_open;    /* TC_COUNT: evaluations the per-wavefront box test shows every
                                     target must open (the node is nearer than s/theta to the box) */
     uint64_t visits_box_accept;  /* TC_COUNT: evaluations the box test shows every target accepts */
+    uint64_t walk_steps;         /* TC_COUNT: traversal steps (each stages one or more sibling groups) */
+    uint64_t walk_single_steps;  /* TC_COUNT: steps that staged a single group */
+    uint64_t visits_overlap;     /* TC_COUNT: evaluations of nodes whose particle range overlaps the
+                                    range of the wavefront's targets (they may hold a target) */
+    uint64_t visits_overlap_all_accept;  /* TC_COUNT: of those, evaluations every active lane accepts */
 } tc_stats;
 
 /* Fill *out.  Synchronises `stream` when diagnostics, timings or a walk's

@@ -53,6 +53,10 @@ class TcStats(ctypes.Structure):
         ("visits_all_accept", ctypes.c_uint64),
         ("visits_box_open", ctypes.c_uint64),
         ("visits_box_accept", ctypes.c_uint64),
+        ("walk_steps", ctypes.c_uint64),
+        ("walk_single_steps", ctypes.c_uint64),
+        ("visits_overlap", ctypes.c_uint64),
+        ("visits_overlap_all_accept", ctypes.c_uint64),
     ]
 
 

@@ -787,6 +787,10 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
             out->visits_box_open = t->host->visits[5];
             out->visits_box_accept = t->host->visits[6];
             out->max_stack = (uint32_t)t->host->visits[7];
+            out->walk_steps = t->host->visits[8];
+            out->walk_single_steps = t->host->visits[9];
+            out->visits_overlap = t->host->visits[10];
+            out->visits_overlap_all_accept = t->host->visits[11];
         }
     }
     if (t->step_valid) {

@@ -147,8 +147,11 @@ struct WalkArgs {
 };
 // counting walk: node evaluations, active lanes, group pops, evaluations with no
 // accepting lane, with every active lane accepting, decided "all open" and "all
-// accept" by the per-wave box test, deepest stack (atomic max)
-constexpr int kNumVisitCounters = 8;
+// accept" by the per-wave box test, deepest stack (atomic max), steps, steps
+// that took a single group, evaluations of nodes whose particle range overlaps
+// the wavefront's targets, of those taken by the general path with every
+// active lane accepting
+constexpr int kNumVisitCounters = 12;
 constexpr uint32_t kListCap = 8192;                     // records per wave (128 KiB)
 constexpr uint32_t kListInvalid = 0xFFFFFFFFu;
 constexpr uint64_t kListMaxBytes = 4ull << 30;          // lists are stored only up to this size

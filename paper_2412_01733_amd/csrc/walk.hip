@@ -41,19 +41,22 @@ constexpr int kWalkWaves = 4;
 constexpr int kWalkThreads = 64 * kWalkWaves;
 // A step of the walk takes up to kBatchGroups sibling groups off the stack and
 // stages all their children at once, 8 lanes per group.
-constexpr int kBatchGroups = 4;
-constexpr int kBatchGroupsF64 = 3;  // the FP64 walk's larger records: 8 waves per SIMD still fit the LDS
+constexpr int kBatchGroups = 5;
+constexpr int kBatchGroupsF64 = 4;  // the FP64 walk's 64-byte staged records (7 waves per SIMD)
 // Stack bound.  Taking one group and pushing the groups of its opened
 // children (at most 8) grows the stack by at most 7 per level below the
 // group, so a depth-first run that starts at height S never exceeds
-// S + 7 * 20 + 1 (groups lie at levels 1..21).  Several groups are taken
-// together only while sp + 7 * kBatchGroups <= kStackBatch, which leaves any
-// batch at height <= kStackBatch; single-group steps from there stay below
+// S + 7 * 20 + 1 (groups lie at levels 1..21).  A step takes ng > 1 groups
+// only while sp + 7 ng <= kStackBatch, which leaves it at height
+// <= kStackBatch; single-group steps from there stay below
 // kStackBatch + 141 <= kStack.  A push beyond the stack therefore cannot
 // happen; it would be refused and flagged (status bit 0).
 constexpr int kStackDfs = 7 * 20 + 1;
-constexpr int kStack = 256;
-constexpr int kStackBatch = kStack - kStackDfs - 7;
+constexpr int kStackMulti = 272;
+// The adjoint walk keeps its gradients in LDS as well; it takes one group per
+// step and a depth-first stack (<= 141 groups), which keeps 7 waves per SIMD.
+constexpr int kStackSingle = 160;
+static_assert(kStackSingle >= kStackDfs, "depth-first stack bound");
 // Stored-list records are staged in LDS and written out this many at a time.
 constexpr uint32_t kListBuf = 32;
 // The adjoint replays stored records this many at a time.
@@ -227,15 +230,25 @@ void k_walk(WalkArgs a)
     constexpr bool FAST = !ADJ && !STORE;
     using R = typename std::conditional<F64, double, float>::type;
     using Hot = typename std::conditional<F64, Hot64, Hot32>::type;
+    // groups per step and the stack they need
+    constexpr int kGroups = ADJ ? 1 : (F64 ? kBatchGroupsF64 : kBatchGroups);
+    constexpr int kStack = kGroups == 1 ? kStackSingle : kStackMulti;
+    constexpr int kStackBatch = kStack - kStackDfs - 7;
     // the stack of pending sibling groups: first node, child count, lanes that opened the parent
-    __shared__ uint32_t stk_gs[kWalkWaves][kStack];
-    __shared__ uint8_t stk_nc[kWalkWaves][kStack];
-    __shared__ uint64_t stk_m[kWalkWaves][kStack];
+    // (several groups per step: three arrays, 13 bytes an entry, so that the deeper stack
+    // fits beside the staging slots; one group per step: one 16-byte record an entry)
+    constexpr int kStackSoa = kGroups > 1 ? kStack : 1;
+    __shared__ uint32_t stk_gs[kWalkWaves][kStackSoa];
+    __shared__ uint8_t stk_nc[kWalkWaves][kStackSoa];
+    __shared__ uint64_t stk_m[kWalkWaves][kStackSoa];
+    __shared__ uint4 stk1[kWalkWaves][kGroups == 1 ? kStack : 1];
     // staged children of the groups of one step: slot 8 j + k holds child k of group j
-    constexpr int kGroups = F64 ? kBatchGroupsF64 : kBatchGroups;
     __shared__ Hot stg[kWalkWaves][8 * kGroups];
     __shared__ uint32_t stg_meta[kWalkWaves][8 * kGroups];
     __shared__ uint4 popped[kWalkWaves][kGroups];  // the step's groups: first node, count, mask
+    // single-group walks: opening thresholds by meta_tau_index (tau0 4^-l at level l, -1 for a
+    // one-particle leaf), one table per wave filled with exact power-of-two scalings
+    __shared__ R taut[kGroups == 1 ? kWalkWaves : 1][64];
     // adjoint: per staged child, the 4 row partials of (dL/dX, dL/dM)
     // adjoint, source side: FP64 walk - per pending node, the 4 row partials of
     // (dL/dX, dL/dM); FP32 walk - per pending node, every lane's 4 values
@@ -256,6 +269,7 @@ void k_walk(WalkArgs a)
     const int64_t wave_id = (int64_t)blockIdx.x * kWalkWaves + w;
     const int64_t base = wave_id * 64;
     if (base >= a.n) return;  // whole wave; no block barrier follows
+    if constexpr (kGroups == 1) taut[w][lane] = lane < 32 ? (R)ldexp(tau0, -2 * (int)lane) : (R)-1;
     // this lane's target (sorted position) and the range of sorted positions the
     // wavefront's targets span (a superset of them: only a node overlapping it
     // can hold one of the targets)
@@ -301,7 +315,7 @@ void k_walk(WalkArgs a)
     uint32_t nint = 0;
     // counting walk: wave-level node evaluations and how they were decided
     uint64_t vis_nodes = 0, vis_lanes = 0, vis_groups = 0, vis_noacc = 0, vis_allacc = 0, vis_boxopen = 0,
-             vis_boxacc = 0;
+             vis_boxacc = 0, vis_steps = 0, vis_single = 0, vis_ovl = 0, vis_slow_acc_ovl = 0;
     int max_sp = 0;
     // The bounding box [bn, bx] of the wavefront's targets (the same offsets the
     // lanes use).  Rounding is monotone, so for a node at X every lane's
@@ -320,7 +334,7 @@ void k_walk(WalkArgs a)
     bnx = uni_r(bnx); bny = uni_r(bny); bnz = uni_r(bnz);
     bxx = uni_r(bxx); bxy = uni_r(bxy); bxz = uni_r(bxz);
 
-    int sp = 0;
+    int sp = 0, since_fold = 0;
     bool stack_over = false, corrupt = false;
 
     // The terms of an opened leaf's particles f .. f+cnt-1 for the lanes in om,
@@ -333,8 +347,10 @@ void k_walk(WalkArgs a)
         const bool lane_open = (om >> lane) & 1ull;
         double mx = xs, my = ys, mz = zs;
         if constexpr (!F64) {
-            const Particle me = a.sp[su];
-            mx = me.x; my = me.y; mz = me.z;
+            // a volatile read stays here, on this rare path: hoisted out of the
+            // walk loop, the position would occupy registers the whole walk
+            const volatile double* me = &a.sp[su].x;
+            mx = me[0]; my = me[1]; mz = me[2];
         }
         for (uint32_t j = f; j < f + cnt; ++j) {
             const Particle pj = a.sp[j];
@@ -506,9 +522,13 @@ void k_walk(WalkArgs a)
         const uint32_t rchild = uni(a.nodes[0].child);
         if (!meta_leaf(rmeta)) {
             if (lane == 0) {
-                stk_gs[w][0] = rchild;
-                stk_nc[w][0] = (uint8_t)meta_nchild(rmeta);
-                stk_m[w][0] = vmask;
+                if constexpr (kGroups == 1) {
+                    stk1[w][0] = make_uint4(rchild, meta_nchild(rmeta), (uint32_t)vmask, (uint32_t)(vmask >> 32));
+                } else {
+                    stk_gs[w][0] = rchild;
+                    stk_nc[w][0] = (uint8_t)meta_nchild(rmeta);
+                    stk_m[w][0] = vmask;
+                }
             }
             sp = 1;
         }
@@ -517,10 +537,20 @@ void k_walk(WalkArgs a)
 
     while (sp > 0) {
         // take ng groups off the top; lanes 8 j .. 8 j + 7 stage the children of group j
-        const int ng = sp <= kStackBatch - 7 * kGroups ? min(sp, kGroups) : 1;
+        // as many groups as the stack bound allows: after the step sp <= kStackBatch
+        const int ng = kGroups > 1 ? max(1, min(min(sp, kGroups), (kStackBatch - sp) / 7)) : 1;
+        if constexpr (COUNT) {
+            vis_steps += 1;
+            vis_single += ng == 1;
+        }
         const int gj = (int)(lane >> 3), gk = (int)(lane & 7);
         uint32_t e_gs = 0, e_nc = 0;
-        if (gj < ng) {
+        uint4 e1 = make_uint4(0, 0, 0, 0);  // single-group walks: the popped record (uniform)
+        if constexpr (kGroups == 1) {
+            e1 = stk1[w][sp - 1];
+            e_gs = e1.x;
+            e_nc = e1.y;
+        } else if (gj < ng) {
             const int slot = sp - 1 - gj;
             e_gs = stk_gs[w][slot];
             e_nc = stk_nc[w][slot];
@@ -545,18 +575,22 @@ void k_walk(WalkArgs a)
             }
             // opening threshold tau0 4^-l (an exact power-of-two scaling); a
             // one-particle leaf is always taken (-1)
-            h.tau = meta_single(nd.meta) ? (R)-1 : (R)ldexp(tau0, -2 * (int)meta_level(nd.meta));
+            if constexpr (kGroups == 1) h.tau = taut[w][meta_tau_index(nd.meta)];
+            else h.tau = meta_single(nd.meta) ? (R)-1 : (R)ldexp(tau0, -2 * (int)meta_level(nd.meta));
             h.first = nd.first;
             h.count = nd.count;
             h.child = nd.child;
             stg[w][lane] = h;
             stg_meta[w][lane] = nd.meta;
-            // the box test (see bn, bx): decided for every target of the wavefront
-            const R gx = fmax(fmax(bnx - h.x, h.x - bxx), (R)0), fx = fmax(fabs(h.x - bnx), fabs(h.x - bxx));
-            const R gy = fmax(fmax(bny - h.y, h.y - bxy), (R)0), fy = fmax(fabs(h.y - bny), fabs(h.y - bxy));
-            const R gz = fmax(fmax(bnz - h.z, h.z - bxz), (R)0), fz = fmax(fabs(h.z - bnz), fabs(h.z - bxz));
-            all_far = !ovl && fma(gx, gx, fma(gy, gy, gz * gz)) > h.tau;
-            all_near = !(fma(fx, fx, fma(fy, fy, fz * fz)) > h.tau);
+            // the box test (see bn, bx): decided for every target of the wavefront;
+            // paid once per step, it pays off when a step stages several groups
+            if constexpr (kGroups > 1) {
+                const R gx = fmax(fmax(bnx - h.x, h.x - bxx), (R)0), fx = fmax(fabs(h.x - bnx), fabs(h.x - bxx));
+                const R gy = fmax(fmax(bny - h.y, h.y - bxy), (R)0), fy = fmax(fabs(h.y - bny), fabs(h.y - bxy));
+                const R gz = fmax(fmax(bnz - h.z, h.z - bxz), (R)0), fz = fmax(fabs(h.z - bnz), fabs(h.z - bxz));
+                all_far = !ovl && fma(gx, gx, fma(gy, gy, gz * gz)) > h.tau;
+                all_near = !(fma(fx, fx, fma(fy, fy, fz * fz)) > h.tau);
+            }
         }
         const uint64_t ovl_m = __ballot(ovl);
         const uint64_t far_all = __ballot(all_far), near_all = __ballot(all_near);
@@ -564,57 +598,75 @@ void k_walk(WalkArgs a)
         wave_sync();
 
         for (int j = 0; j < ng; ++j) {
-            const uint4 e = popped[w][j];
-            const uint32_t gs = uni(e.x);
-            const uint32_t nc = min(uni(e.y), 8u);
-            const uint64_t mask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
+            uint32_t gs, nc;
+            uint64_t mask;
+            if constexpr (kGroups == 1) {
+                gs = uni(e1.x);
+                nc = min(uni(e1.y), 8u);
+                mask = ((uint64_t)uni(e1.w) << 32) | uni(e1.z);
+            } else {
+                const uint4 e = popped[w][j];
+                gs = uni(e.x);
+                nc = min(uni(e.y), 8u);
+                mask = ((uint64_t)uni(e.w) << 32) | uni(e.z);
+            }
             if constexpr (COUNT) {
                 vis_nodes += nc;
                 vis_lanes += (uint64_t)nc * (uint64_t)__popcll(mask);
                 vis_groups += 1;
+                vis_ovl += __popc((uint32_t)(ovl_m >> (8 * j)) & ((1u << nc) - 1u));
             }
             const uint32_t all = (1u << nc) - 1u;
             // decided accepted by every target, and not holding any (the forward
-            // walks take these in one straight run with the active lanes enabled)
-            uint32_t fast = FAST ? (uint32_t)(far_all >> (8 * j)) & all : 0u;
+            // walks take these in one straight run with the active lanes enabled;
+            // the others take them through the general path without the tests)
+            const uint32_t far_bits = (uint32_t)(far_all >> (8 * j)) & all;
+            uint32_t fast = FAST ? far_bits : 0u;
             // decided opened by every active target
             uint32_t opened = (uint32_t)(near_all >> (8 * j)) & all & ~fast;
-            uint32_t slow = all & ~fast & ~opened;
+            const uint32_t slow = all & ~fast & ~opened;
             if constexpr (COUNT) {
                 vis_allacc += __popc(fast);
                 vis_boxacc += __popc(fast);
                 vis_noacc += __popc(opened);
                 vis_boxopen += __popc(opened);
             }
+            const Hot* g8 = &stg[w][8 * j];
             if (fast && __builtin_amdgcn_inverse_ballot_w64(mask)) {
-                do {
-                    const uint32_t k = __builtin_ctz(fast);
-                    fast &= fast - 1u;
-                    const Hot h = stg[w][8u * (uint32_t)j + k];
-                    const R dx = h.x - px, dy = h.y - py, dz = h.z - pz;
-                    const R d2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                    const R ri = rsqrt_any(d2 + eps2);
-                    const R mr = h.m * ri;
-                    const R mr3 = mr * (ri * ri);
-                    bx = fma(mr3, dx, bx);
-                    by = fma(mr3, dy, by);
-                    bz = fma(mr3, dz, bz);
-                    bp -= mr;
-                    if constexpr (COUNT) ++nint;
-                } while (fast);
+                // no opening test here, so the softening enters the distance chain
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if ((fast >> k) & 1u) {
+                        const Hot h = g8[k];
+                        const R dx = h.x - px, dy = h.y - py, dz = h.z - pz;
+                        const R ri = rsqrt_any(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
+                        const R mr = h.m * ri;
+                        const R mr3 = mr * (ri * ri);
+                        bx = fma(mr3, dx, bx);
+                        by = fma(mr3, dy, by);
+                        bz = fma(mr3, dz, bz);
+                        bp -= mr;
+                        if constexpr (COUNT) ++nint;
+                    }
+                }
             }
             // an opened child: its own group is pushed, or an opened leaf's particles
             // are taken one by one, the target itself excluded (for a one-particle
             // leaf only the lane holding that particle gets here, and it contributes nothing)
-            auto open_child = [&](const uint32_t slot, const uint32_t k, const uint64_t om) {
+            auto open_child = [&](const uint32_t slot, const uint32_t k, const uint64_t om, const uint32_t child_v,
+                                  const uint32_t first_v, const uint32_t count_v) {
                 const uint32_t meta = uni(stg_meta[w][slot]);
                 if (!meta_leaf(meta)) {
-                    const uint32_t child = uni(stg[w][slot].child);
+                    const uint32_t child = uni(child_v);
                     if (sp < kStack) {
                         if (lane == 0) {
-                            stk_gs[w][sp] = child;
-                            stk_nc[w][sp] = (uint8_t)meta_nchild(meta);
-                            stk_m[w][sp] = om;
+                            if constexpr (kGroups == 1) {
+                                stk1[w][sp] = make_uint4(child, meta_nchild(meta), (uint32_t)om, (uint32_t)(om >> 32));
+                            } else {
+                                stk_gs[w][sp] = child;
+                                stk_nc[w][sp] = (uint8_t)meta_nchild(meta);
+                                stk_m[w][sp] = om;
+                            }
                         }
                         sp = uni(sp + 1);
                         if constexpr (COUNT) max_sp = max(max_sp, sp);
@@ -622,7 +674,7 @@ void k_walk(WalkArgs a)
                         stack_over = true;
                     }
                 } else {
-                    const uint32_t f = uni(stg[w][slot].first), cnt = uni(stg[w][slot].count);
+                    const uint32_t f = uni(first_v), cnt = uni(count_v);
                     if (cnt > 1) {
                         leaf_terms(f, cnt, om);
                         if constexpr (STORE) list_put(gs + k, 1u, om);
@@ -632,23 +684,26 @@ void k_walk(WalkArgs a)
             while (opened) {
                 const uint32_t k = __builtin_ctz(opened);
                 opened &= opened - 1u;
-                open_child(8u * (uint32_t)j + k, k, mask);
-            }
-            while (slow) {
-                const uint32_t k = __builtin_ctz(slow);
-                slow &= slow - 1u;
                 const uint32_t slot = 8u * (uint32_t)j + k;
-                const Hot h = stg[w][slot];  // one broadcast read of the whole record
+                open_child(slot, k, mask, stg[w][slot].child, stg[w][slot].first, stg[w][slot].count);
+            }
+            // the general path: per-lane opening test, containment where the child may hold a target
+            auto general = [&](const uint32_t k) {
+                const uint32_t slot = 8u * (uint32_t)j + k;
+                const Hot h = g8[k];  // one broadcast read of the whole record
                 const R dx = h.x - px, dy = h.y - py, dz = h.z - pz;
                 const R d2 = fma(dx, dx, fma(dy, dy, dz * dz));
                 // lane masks combined on the scalar unit: accepted = active, not containing, far enough
-                uint64_t in_m = 0;
-                if ((ovl_m >> slot) & 1ull) in_m = __ballot((su - h.first) < h.count);
-                const uint64_t far_m = __ballot(d2 > h.tau);
-                const uint64_t am = mask & far_m & ~in_m;
+                uint64_t am = mask;
+                if (FAST || !((far_bits >> k) & 1u)) {
+                    uint64_t in_m = 0;
+                    if ((ovl_m >> slot) & 1ull) in_m = __ballot((su - h.first) < h.count);
+                    am &= __ballot(d2 > h.tau) & ~in_m;
+                }
                 if constexpr (COUNT) {
                     vis_noacc += am == 0;
                     vis_allacc += am == mask;
+                    vis_slow_acc_ovl += am == mask && ((ovl_m >> slot) & 1ull);
                 }
                 if constexpr (!ADJ) {
                     if (__builtin_amdgcn_inverse_ballot_w64(am)) {
@@ -677,11 +732,32 @@ void k_walk(WalkArgs a)
                     }
                 }
                 const uint64_t om = mask & ~am;
-                if (om) open_child(slot, k, om);
+                if (om) open_child(slot, k, om, h.child, h.first, h.count);
+            };
+            if constexpr (kGroups == 1) {
+                // one group per step (the adjoint): unrolled over the children,
+                // records read at fixed offsets
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    if ((uint32_t)k >= nc) break;
+                    if ((slow >> k) & 1u) general((uint32_t)k);
+                }
+            } else {
+                for (uint32_t rest = slow; rest;) {
+                    const uint32_t k = __builtin_ctz(rest);
+                    rest &= rest - 1u;
+                    general(k);
+                }
             }
         }
         wave_sync();  // the next step restages the slots and rereads the stack
-        fold();
+        // a step adds up to ~30 terms per lane to the plain partial sums; they go
+        // into the compensated totals every second step (every fourth for
+        // single-group steps)
+        if (++since_fold == (kGroups == 1 ? 4 : 2) || sp == 0) {
+            since_fold = 0;
+            fold();
+        }
     }
     if (lane == 0 && (stack_over || corrupt)) atomicOr(a.status, (stack_over ? 1u : 0u) | (corrupt ? 2u : 0u));
     if constexpr (ADJ) src_flush();
@@ -739,6 +815,10 @@ void k_walk(WalkArgs a)
             atomicAdd(&a.visits[5], (unsigned long long)vis_boxopen);
             atomicAdd(&a.visits[6], (unsigned long long)vis_boxacc);
             atomicMax(&a.visits[7], (unsigned long long)max_sp);
+            atomicAdd(&a.visits[8], (unsigned long long)vis_steps);
+            atomicAdd(&a.visits[9], (unsigned long long)vis_single);
+            atomicAdd(&a.visits[10], (unsigned long long)vis_ovl);
+            atomicAdd(&a.visits[11], (unsigned long long)vis_slow_acc_ovl);
         }
     }
 }

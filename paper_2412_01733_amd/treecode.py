@@ -221,7 +221,10 @@ class Tree:
                     stage_ms=list(s.stage_ms), lists_stored=bool(s.lists_stored),
                     max_stack=int(s.max_stack), group_pops=int(s.group_pops),
                     visits_no_accept=int(s.visits_no_accept), visits_all_accept=int(s.visits_all_accept),
-                    visits_box_open=int(s.visits_box_open), visits_box_accept=int(s.visits_box_accept))
+                    visits_box_open=int(s.visits_box_open), visits_box_accept=int(s.visits_box_accept),
+                    walk_steps=int(s.walk_steps), walk_single_steps=int(s.walk_single_steps),
+                    visits_overlap=int(s.visits_overlap),
+                    visits_overlap_all_accept=int(s.visits_overlap_all_accept))
 
     def export(self, moments=True):
         st = self.stats()
