@@ -213,7 +213,7 @@ typedef struct {
 /* Fill *out.  Synchronises `stream` when diagnostics, timings or a walk's
  * status are pending.
  * Errors: TC_ERR_INVALID (null pointer); after filling *out, the status of
- * the walks since the last check: TC_ERR_OVERFLOW if a traversal stack would
+ * the walks since the last build: TC_ERR_OVERFLOW if a traversal stack would
  * have overflowed (terms dropped), TC_ERR_DEVICE if a walk met a node with
  * more than 8 children.  Neither can happen for a tree built by tc_build: the
  * traversal stack is sized from the depth bound of the octree. */

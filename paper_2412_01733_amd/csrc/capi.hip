@@ -255,10 +255,11 @@ tc_status mark_done(tc_tree* t, hipStream_t s, tc_status st)
     return st;
 }
 
-// Status word of the walks (bit 0: a traversal stack would have overflowed, so
-// terms were dropped; bit 1: a node with more than 8 children, i.e. a corrupt
-// tree).  Neither can happen for a tree built by tc_build (the stack bound is
-// proven in walk.hip); both are checked wherever the host synchronises anyway.
+// Status word of the walks, cleared by each build and kept until the next
+// (bit 0: a traversal stack would have overflowed, so terms were dropped;
+// bit 1: a node with more than 8 children, i.e. a corrupt tree).  Neither can
+// happen for a tree built by tc_build (the stack bound is proven in
+// walk.hip); both are checked wherever the host synchronises anyway.
 tc_status walk_status_error(tc_tree* t)
 {
     if (!t->walk_status_pending) return TC_OK;
@@ -370,6 +371,7 @@ tc_status build_impl(tc_tree* t, const void* pos, const void* mass, int64_t n, t
     TC_TRY(ensure(t, t->parent, m4, s));
     TC_TRY(ensure(t, t->topo, (size_t)nn * 16, s));
 
+    launch_fill_u32(t->status, 1, 0u, s);  // status bits stay set until the next build
     launch_emit_nodes(t->skeys, P<int8_t>(t->c), P<uint32_t>(t->pre), n, P<uint8_t>(t->level), P<uint32_t>(t->first),
                       P<uint32_t>(t->count), P<uint32_t>(t->next), P<uint8_t>(t->octant), s);
     launch_count_children(P<uint8_t>(t->level), P<uint32_t>(t->count), P<uint32_t>(t->next), nn,
@@ -461,7 +463,6 @@ tc_status forces_impl(tc_tree* t, double theta, double eps, double G, tc_walk mo
         a.list_cap = kListCap;
     }
 
-    launch_fill_u32(t->status, 1, 0u, s);
     if (t->counted) launch_fill_u32((uint32_t*)t->visits, 2 * kNumVisitCounters, 0u, s);
     stage_begin(t, kStWalk, s);
     launch_walk(a, mode, t->counted, store, s);
@@ -510,7 +511,6 @@ tc_status backward_impl(tc_tree* t, const void* g_acc, const void* g_pot, void* 
     stage_begin(t, kStBwdWalk, s);
     launch_fill_f64_zero(a.node_grad, nn * 4, s);
     launch_fill_f64_zero(a.part_grad, n * 4, s);
-    launch_fill_u32(t->status, 1, 0u, s);
     launch_walk_adjoint(a, t->last_mode, s);
     stage_end(t, kStBwdWalk, s);
     TC_TRY(check_launch("adjoint walk"));
