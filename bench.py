@@ -134,16 +134,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def adjoint_leg(tc, workloads, torch, dev, args):
-    """fwd+adjoint ms against forward-only ms: Plummer N = 2^18, masses
-    perturbed log-normally (sigma = 0.2), loss = mean |a - a*|^2 with a* the
-    field of the unperturbed masses, theta = 0.5, eps = 0.01, FP32 walk.  The
-    backward re-walks the tree with the forward's decisions; the variant whose
-    forward stores the interaction lists for the backward to replay is timed
-    beside it."""
-    n, theta, eps = 1 << 18, 0.5, 0.01
-    pos_np, _ = workloads.plummer(n, 1003, dtype=np.float32)
-    m_np = workloads.lognormal_masses(n, 2003).astype(np.float32)
+def adjoint_leg(tc, workloads, torch, dev, args, n=1 << 18, eps=0.01, seeds=(1003, 2003), stored=True):
+    """fwd+adjoint ms against forward-only ms: a Plummer sphere (N = 2^18 by
+    default, the fitting workload; also run at N = 1e7, the headline size, where
+    the walk fills the GPU), masses perturbed log-normally (sigma = 0.2), loss =
+    mean |a - a*|^2 with a* the field of the unperturbed masses, theta = 0.5, FP32
+    walk.  The backward re-walks the tree with the forward's decisions; the
+    variant whose forward stores the interaction lists for the backward to
+    replay is timed beside it (where the lists fit)."""
+    theta = 0.5
+    pos_np, _ = workloads.plummer(n, seeds[0], dtype=np.float32)
+    m_np = workloads.lognormal_masses(n, seeds[1]).astype(np.float32)
     pos = torch.from_numpy(pos_np).to(dev)
     m_true = torch.full((n,), 1.0 / n, dtype=torch.float32, device=dev)
     mass = torch.from_numpy(m_np).to(dev)
@@ -162,7 +163,7 @@ def adjoint_leg(tc, workloads, torch, dev, args):
         return tree.backward(g, None)
 
     res = {}
-    legs = (("fwd", fwd), ("fwd_adj", fwd_adj), ("fwd_adj_stored", lambda: fwd_adj(True)))
+    legs = (("fwd", fwd), ("fwd_adj", fwd_adj)) + ((("fwd_adj_stored", lambda: fwd_adj(True)),) if stored else ())
     for name, fn in legs:
         for _ in range(args.warmup):
             fn()
@@ -175,16 +176,59 @@ def adjoint_leg(tc, workloads, torch, dev, args):
     tree.set_timing(True)
     fwd_adj(False)
     st = tree.stats()
-    fwd_adj(True)
-    st_sl = tree.stats()
+    st_sl = None
+    if stored:
+        fwd_adj(True)
+        st_sl = tree.stats()
     tree.set_timing(False)
-    log("bench: adjoint leg N=%d: fwd %.3f ms, fwd+adjoint %.3f ms (with stored lists %.3f ms)" %
-        (n, res["fwd"], res["fwd_adj"], res["fwd_adj_stored"]))
-    return dict(workload="plummer-N262144-lognormal-masses-theta0.5-eps0.01", n=n, walk="f32c",
-                fwd_ms=res["fwd"], fwd_adj_ms=res["fwd_adj"], ratio=res["fwd_adj"] / res["fwd"],
-                fwd_walk_ms=st["stage_ms"][4], bwd_walk_ms=st["stage_ms"][6], bwd_down_ms=st["stage_ms"][7],
-                stored_lists=dict(fwd_adj_ms=res["fwd_adj_stored"], lists_stored=st_sl["lists_stored"],
-                                  fwd_walk_ms=st_sl["stage_ms"][4], bwd_walk_ms=st_sl["stage_ms"][6]))
+    log("bench: adjoint leg N=%d: fwd %.3f ms, fwd+adjoint %.3f ms (walks %.3f / %.3f ms)" %
+        (n, res["fwd"], res["fwd_adj"], st["stage_ms"][4], st["stage_ms"][6]))
+    out = dict(workload="plummer-N%d-lognormal-masses-theta0.5-eps%g" % (n, eps), n=n, walk="f32c",
+               fwd_ms=res["fwd"], fwd_adj_ms=res["fwd_adj"], ratio=res["fwd_adj"] / res["fwd"],
+               fwd_walk_ms=st["stage_ms"][4], bwd_walk_ms=st["stage_ms"][6], bwd_down_ms=st["stage_ms"][7],
+               walk_ratio=st["stage_ms"][6] / st["stage_ms"][4])
+    if stored:
+        out["stored_lists"] = dict(fwd_adj_ms=res["fwd_adj_stored"], lists_stored=st_sl["lists_stored"],
+                                   fwd_walk_ms=st_sl["stage_ms"][4], bwd_walk_ms=st_sl["stage_ms"][6])
+    return out
+
+
+def bh_gradient_error(tc, workloads, torch, dev, oracle):
+    """The direct-sum reference gradient at N = 4096 (Plummer, log-normal
+    masses, eps = 0.01, L = mean |a - a*|^2, a* the direct field of the
+    unperturbed masses): the gradient with the Barnes-Hut field (FP64 walk and
+    its adjoint) at theta = 0 and 0.5 against the one with the direct-sum field
+    (the oracle's frozen-list adjoint of the theta = 0 lists).  At theta = 0.5 the
+    difference is the method's own approximation error."""
+    n, eps = 4096, 0.01
+    x, _ = workloads.plummer(n, 4003)
+    m = workloads.lognormal_masses(n, 4004)
+    astar, _ = oracle.direct(x, np.full(n, 1.0 / n), eps)
+    T = oracle.Tree(x, m)
+    ad, _ = oracle.direct(x, m, eps)
+    gx_d, gm_d = T.frozen_adjoint(T.lists(0.0), eps, (2.0 / n) * (ad - astar))
+    t = tc.Tree().build(torch.from_numpy(x).to(dev), torch.from_numpy(m).to(dev)).moments()
+    out = dict(n=n, eps=eps, walk="f64")
+    for theta in (0.0, 0.5):
+        a, _ = t.forces(theta, eps, walk="f64")
+        g = (2.0 / n) * (a.cpu().numpy() - astar)
+        gpos, gmass = t.backward(torch.from_numpy(g).to(dev))
+        ex = np.linalg.norm(gpos.cpu().numpy() - gx_d, axis=1) / np.linalg.norm(gx_d, axis=1)
+        em = np.abs(gmass.cpu().numpy() - gm_d) / np.abs(gm_d)
+        out["theta%g" % theta] = dict(dLdx_median=float(np.median(ex)), dLdx_p99=float(np.quantile(ex, 0.99)),
+                                      dLdm_median=float(np.median(em)), dLdm_p99=float(np.quantile(em, 0.99)))
+    return out
+
+
+def cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -294,6 +338,8 @@ def main():
     adj = None
     if not args.no_adjoint:
         adj = adjoint_leg(tc, workloads, torch, dev, args)
+        adj["full_size"] = adjoint_leg(tc, workloads, torch, dev, args, n=n, eps=args.eps, seeds=(args.seed, 2002),
+                                       stored=False)
 
     out_acc = {}
     cpu = None
@@ -310,7 +356,7 @@ def main():
         ra, rp, rn = T.forces(args.theta, args.eps, targets=tg, nthreads=nthreads)
         t_walk = time.perf_counter() - tw0
         t_full = t_build + t_walk * n / len(tg)
-        cpu = dict(value=n / t_full, unit="particle-forces/s", cores=nthreads, kind="oracle",
+        cpu = dict(value=n / t_full, unit="particle-forces/s", cores=nthreads, model=cpu_model(), kind="oracle",
                    sample="full-N build (1 thread, %.2f s) + walk of %d seeded targets (%d threads, %.2f s), "
                           "extrapolated to N" % (t_build, len(tg), nthreads, t_walk))
         k = min(args.acc_sample, len(tg))
@@ -325,6 +371,9 @@ def main():
                                  targets=int(k))
         oracle_inter = int(rn.sum())
         cpu["oracle_interactions_per_target"] = oracle_inter / len(tg)
+        if adj is not None:
+            log("bench: Barnes-Hut gradient against the direct-sum gradient, N=4096 ...")
+            adj["bh_vs_direct_gradient"] = bh_gradient_error(tc, workloads, torch, dev, oracle)
 
     head = walks[0]
     r = res[head]

@@ -69,7 +69,7 @@ def lib():
         PP = ctypes.POINTER(ctypes.POINTER(ctypes.c_int64))
         L.or_tree_lists.argtypes = [P, D, PP, PP, ctypes.c_int]
         L.or_free.argtypes = [P]
-        L.or_frozen_forces.argtypes = [P, P, P, P, P, D, D, P, P]
+        L.or_frozen_forces.argtypes = [P, P, P, P, P, D, D, P, P, ctypes.c_int]
         L.or_frozen_adjoint.argtypes = [P, P, P, D, D, P, P, P, P]
         L.or_leapfrog_step.argtypes = [P, P, P, P, P, I64, D, D, D, D, ctypes.c_int]
         L.or_leapfrog_step.restype = ctypes.c_int
@@ -207,15 +207,16 @@ class Tree:
         lib().or_free(ctypes.cast(cod, ctypes.c_void_p))
         return o, c
 
-    def frozen_forces(self, pos, mass, lists, eps, G=1.0):
-        """F(x, m; lists): forces with this tree's membership and the given lists frozen."""
+    def frozen_forces(self, pos, mass, lists, eps, G=1.0, nthreads=1):
+        """F(x, m; lists): forces with this tree's membership and the given lists frozen
+        (targets shared by nthreads; the result does not depend on it)."""
         x = _f64pos(pos)
         m = np.ascontiguousarray(np.asarray(mass, dtype=np.float64).reshape(-1))
         o, c = lists
         acc = np.zeros((self.n, 3))
         pot = np.zeros(self.n)
         lib().or_frozen_forces(self._h, _ptr(x), _ptr(m), _ptr(o), _ptr(c), float(eps), float(G),
-                               _ptr(acc), _ptr(pot))
+                               _ptr(acc), _ptr(pot), _threads(nthreads))
         return acc, pot
 
     def frozen_adjoint(self, lists, eps, g_acc, g_pot=None, G=1.0):

@@ -656,10 +656,36 @@ static void frozen_moments(const or_tree* T, const double* pos, const double* m,
     }
 }
 
+typedef struct {
+    const or_tree* T;
+    const double *sx, *sm, *com, *mass;
+    const int64_t *offsets, *codes;
+    double eps2, G;
+    double* acc;
+    double* pot;
+} frozen_job;
+
+/* one target's frozen list, summed in list order */
+static void frozen_task(void* p, int64_t i)
+{
+    frozen_job* J = (frozen_job*)p;
+    int64_t si = J->T->spos[i];
+    acc_t r;
+    memset(&r, 0, sizeof r);
+    for (int64_t q = J->offsets[i]; q < J->offsets[i + 1]; ++q) {
+        int64_t c = J->codes[q];
+        if (c >= 0) term(&r, &J->sx[3 * si], &J->com[3 * c], J->mass[c], J->eps2, J->G);
+        else term(&r, &J->sx[3 * si], &J->sx[3 * (-c - 1)], J->sm[-c - 1], J->eps2, J->G);
+    }
+    for (int k = 0; k < 3; ++k) J->acc[3 * i + k] = r.a[k];
+    if (J->pot) J->pot[i] = r.phi;
+}
+
 /* F(x, m; lists): accelerations and potentials (caller order) with the tree
- * membership and the lists frozen. */
+ * membership and the lists frozen.  Targets are independent: nthreads share
+ * them, each target's sum is the same whatever the thread count. */
 void or_frozen_forces(const or_tree* T, const double* pos, const double* m, const int64_t* offsets,
-                      const int64_t* codes, double eps, double G, double* acc, double* pot)
+                      const int64_t* codes, double eps, double G, double* acc, double* pot, int nthreads)
 {
     int64_t n = T->n, nn = T->nn;
     double* sx = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
@@ -667,19 +693,10 @@ void or_frozen_forces(const or_tree* T, const double* pos, const double* m, cons
     double* com = (double*)malloc(sizeof(double) * 3 * (size_t)(nn > 0 ? nn : 1));
     double* mass = (double*)malloc(sizeof(double) * (size_t)(nn > 0 ? nn : 1));
     frozen_moments(T, pos, m, sx, sm, com, mass);
-    double eps2 = eps * eps;
-    for (int64_t i = 0; i < n; ++i) {
-        int64_t si = T->spos[i];
-        acc_t r;
-        memset(&r, 0, sizeof r);
-        for (int64_t q = offsets[i]; q < offsets[i + 1]; ++q) {
-            int64_t c = codes[q];
-            if (c >= 0) term(&r, &sx[3 * si], &com[3 * c], mass[c], eps2, G);
-            else term(&r, &sx[3 * si], &sx[3 * (-c - 1)], sm[-c - 1], eps2, G);
-        }
-        for (int k = 0; k < 3; ++k) acc[3 * i + k] = r.a[k];
-        if (pot) pot[i] = r.phi;
-    }
+    frozen_job J;
+    J.T = T; J.sx = sx; J.sm = sm; J.com = com; J.mass = mass;
+    J.offsets = offsets; J.codes = codes; J.eps2 = eps * eps; J.G = G; J.acc = acc; J.pot = pot;
+    run_parallel(frozen_task, &J, n, nthreads);
     free(sx); free(sm); free(com); free(mass);
 }
 

@@ -165,3 +165,14 @@ def test_leapfrog_circular_two_body_orbit():
     assert np.abs(x[0] - want).max() < 2e-5  # leapfrog phase error ~ (omega tau)^2 omega t / 24
     # the separation oscillates with relative amplitude ~ (omega tau)^2 / 8
     assert abs(np.linalg.norm(x[0] - x[1]) - 1.0) < 2e-5
+
+
+def test_frozen_forces_do_not_depend_on_the_thread_count():
+    """Targets are independent: sharing them among threads leaves every sum,
+    and so every bit of the result, unchanged."""
+    x, m = workloads.plummer(3000, 17)
+    T = oracle.Tree(x, m)
+    L = T.lists(0.6)
+    a1, p1 = T.frozen_forces(x, m, L, 0.01, nthreads=1)
+    a8, p8 = T.frozen_forces(x, m, L, 0.01, nthreads=8)
+    assert (a1 == a8).all() and (p1 == p8).all()
