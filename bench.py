@@ -36,6 +36,8 @@ if ROOT not in sys.path:
 FLOPS_PER_INTERACTION = 20          # acc + pot, rsqrt counted as one
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_f32c_plummer1e7_traffic.txt")
 WALK_SRC = os.path.join(ROOT, "paper_2412_01733_amd", "csrc", "walk.hip")
+BUILD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "build_plummer1e7_traffic.md")
+BUILD_SRCS = ["keys.hip", "sort.hip", "scan.hip", "build.hip", "moments.hip", "order.hip"]
 PEAK_FP32_TFLOPS = 157.3             # MI355X FP32 vector (packed FMA)
 PEAK_FP32_NONPACKED_TFLOPS = 78.6    # one FMA per lane per clock: 256 CU x 64 lanes x 2 x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6
@@ -56,16 +58,39 @@ def walk_traffic_bytes():
     """HBM bytes per walk launch from the committed rocprofv3 counter summary,
     or None if the walk's code changed since the counters were taken."""
     try:
-        kv = {}
-        for line in open(TRAFFIC_FILE):
-            if "=" in line and not line.startswith("#"):
-                k, v = line.split("=", 1)
-                kv[k.strip()] = v.strip()
+        kv = read_kv(TRAFFIC_FILE)
         if kv.get("walk_hip_code_sha256") != code_hash(WALK_SRC):
             return None
         fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
         write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
         return (fetch + write) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def read_kv(path):
+    """`key = value` lines of a committed profile summary."""
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    return kv
+
+
+def build_counter_bytes():
+    """Per-stage HBM bytes of one build at Plummer N = 1e7 from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None if a build source
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = read_kv(BUILD_TRAFFIC_FILE)
+        h = hashlib.sha256()
+        for f in BUILD_SRCS:
+            h.update(code_hash(os.path.join(ROOT, "paper_2412_01733_amd", "csrc", f)).encode())
+        if kv.get("build_src_sha256") != h.hexdigest():
+            return None
+        return {k: float(kv["stage_%s_bytes" % k]) for k in ("keys", "sort", "tree", "moments")}
     except (OSError, KeyError, ValueError):
         return None
 
@@ -378,11 +403,15 @@ def main():
     head = walks[0]
     r = res[head]
     sb = stage_bytes(n, r["n_nodes"])
+    cb = build_counter_bytes() if (n == 10_000_000 and args.seed == 1002) else None
     hbm = {}
     for k, b in sb.items():
         ms = r["stage_ms"][k]
         gbps = b / (ms * 1e-3) / 1e9 if ms > 0 else None
         hbm[k] = dict(bytes=int(b), ms=ms, GBps=gbps, frac=(gbps / PEAK_HBM_GBPS) if gbps else None)
+        if cb is not None:
+            cg = cb[k] / (ms * 1e-3) / 1e9 if ms > 0 else None
+            hbm[k].update(counter_bytes=int(cb[k]), counter_GBps=cg, counter_frac=(cg / PEAK_HBM_GBPS) if cg else None)
     copy_gbps = copy_bandwidth(torch, dev)
     flops = FLOPS_PER_INTERACTION * r["interactions"]
     achieved = flops / (r["walk_ms"] * 1e-3) / 1e12
@@ -409,7 +438,9 @@ def main():
                      "walk_ms": r["walk_ms"],
                      "frac_nonpacked_fp32": (achieved / PEAK_FP32_NONPACKED_TFLOPS) if head == "f32c" else None},
         "build_hbm": {"peak_GBps": PEAK_HBM_GBPS, "copy_GBps": copy_gbps, "stages": hbm,
-                      "note": "compulsory bytes per stage (see stage_bytes) over the stage's HIP-event time"},
+                      "note": "bytes: compulsory bytes per stage (stage_bytes); counter_bytes: rocprofv3 FETCH_SIZE x 2 + "
+                              "WRITE_SIZE of the same build (profiles/build_plummer1e7_traffic.md, null if the build "
+                              "code changed); both over the stage's HIP-event time"},
         "gpu_clocks": gpu_clocks(),
         "cpu_baseline": cpu,
         "adjoint": adj,
