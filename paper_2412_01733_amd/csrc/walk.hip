@@ -250,7 +250,6 @@ void k_walk(WalkArgs a)
     // single-group walks: opening thresholds by meta_tau_index (tau0 4^-l at level l, -1 for a
     // one-particle leaf), one table per wave filled with exact power-of-two scalings
     __shared__ R taut[kGroups == 1 ? kWalkWaves : 1][64];
-    // adjoint: per staged child, the 4 row partials of (dL/dX, dL/dM)
     // adjoint, source side: FP64 walk - per pending node, the 4 row partials of
     // (dL/dX, dL/dM); FP32 walk - per pending node, every lane's 4 values
     constexpr int kSrcBatch = F64 ? 8 : 2;

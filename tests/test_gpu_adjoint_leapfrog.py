@@ -297,7 +297,7 @@ def test_adjoint_full_size_finite_differences():
 
 
 def test_bh_gradient_against_direct_sum_gradient():
-    """cfg3's direct-sum reference at N = 4096: the gradient of
+    """The direct-sum reference gradient at N = 4096: the gradient of
     L = mean |a - a*|^2 with the Barnes-Hut field (theta = 0.5, FP64 walk and
     its adjoint) against the gradient with the direct-sum field (the oracle's
     frozen-list adjoint of the theta = 0 lists).  At theta = 0 the two must
