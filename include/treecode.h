@@ -219,6 +219,15 @@ typedef struct {
  * traversal stack is sized from the depth bound of the octree. */
 tc_status tc_tree_stats(tc_tree* tree, tc_stats* out, void* stream);
 
+/* Testing hook for the error path above: sets the handle's walk status word
+ * on the device to `bits` (bit 0: a refused stack push, bit 1: a node with more
+ * than 8 children), on `stream`, as a walk that met either would leave it, so
+ * that callers and tests can see how tc_tree_stats and the next tc_build report
+ * it.  No kernel is made to misbehave.  The next tc_build clears the word.
+ * Errors: TC_ERR_INVALID (null tree, bits outside 0..3), TC_ERR_STATE (no
+ * tc_build on the handle). */
+tc_status tc_tree_set_walk_status(tc_tree* tree, uint32_t bits, void* stream);
+
 /* Record per-stage durations with HIP events on the call's stream (off by
  * default).  Errors: TC_ERR_INVALID (null tree). */
 tc_status tc_tree_set_timing(tc_tree* tree, int on);

@@ -20,7 +20,8 @@ TC_COUNT, TC_STORE_LISTS = 1, 2
 
 # Every exported symbol of the C ABI, as declared in include/treecode.h.
 EXPORTS = ("tc_set_allocator", "tc_build", "tc_moments", "tc_forces", "tc_forces_backward",
-           "tc_forces_noalloc", "tc_leapfrog_step", "tc_tree_stats", "tc_tree_set_timing", "tc_tree_export",
+           "tc_forces_noalloc", "tc_leapfrog_step", "tc_tree_stats", "tc_tree_set_walk_status",
+           "tc_tree_set_timing", "tc_tree_export",
            "tc_interaction_counts", "tc_tree_target_order", "tc_tree_free", "tc_last_error", "tc_version")
 
 
@@ -99,6 +100,8 @@ def load():
     L.tc_leapfrog_step.restype = st
     L.tc_tree_stats.argtypes = [P, ctypes.POINTER(TcStats), P]
     L.tc_tree_stats.restype = st
+    L.tc_tree_set_walk_status.argtypes = [P, ctypes.c_uint32, P]
+    L.tc_tree_set_walk_status.restype = st
     L.tc_tree_set_timing.argtypes = [P, I]
     L.tc_tree_set_timing.restype = st
     L.tc_tree_export.argtypes = [P, P, P, P, P, P, P, P, P]

@@ -744,6 +744,21 @@ tc_status tc_leapfrog_step(tc_tree** tree, void* pos, void* vel, const void* mas
 }
 
 
+tc_status tc_tree_set_walk_status(tc_tree* t, uint32_t bits, void* stream)
+{
+    g_err.clear();
+    if (!t) return fail(TC_ERR_INVALID, "tc_tree_set_walk_status: NULL tree");
+    if (bits > 3u) return fail(TC_ERR_INVALID, "tc_tree_set_walk_status: bits must be within 0..3");
+    if (!(t->state & 1u)) return fail(TC_ERR_STATE, "tc_tree_set_walk_status: no successful tc_build on this handle");
+    TC_TRY(check_device(t));
+    hipStream_t s = (hipStream_t)stream;
+    launch_fill_u32(t->status, 1, bits, s);
+    TC_TRY(check_launch("status"));
+    HIP_TRY(hipMemcpyAsync(&t->host->status, t->status, 4, hipMemcpyDeviceToHost, s));
+    t->walk_status_pending = true;
+    return mark_done(t, s, TC_OK);
+}
+
 tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
 {
     g_err.clear();

@@ -61,6 +61,7 @@ def test_argument_validation_without_device():
     assert L.tc_forces_backward(None, None, None, None, None, None) == m.TC_ERR_INVALID
     assert L.tc_tree_stats(None, None, None) == m.TC_ERR_INVALID
     assert L.tc_tree_set_timing(None, 1) == m.TC_ERR_INVALID
+    assert L.tc_tree_set_walk_status(None, 1, None) == m.TC_ERR_INVALID
     assert L.tc_tree_export(None, None, None, None, None, None, None, None, None) == m.TC_ERR_INVALID
     assert L.tc_interaction_counts(None, None, None) == m.TC_ERR_INVALID
     assert L.tc_tree_target_order(None, None, None) == m.TC_ERR_INVALID

@@ -2,7 +2,10 @@
 buffers are checked before any launch (a wrong shape, dtype, layout or a
 strided view that would be updated through a copy raises and leaves the
 buffers untouched), the library's buffers come from torch's caching
-allocator, and the walk status is clean after every walk kind."""
+allocator, and the walk status is clean after every walk kind and reported
+when set."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -116,3 +119,37 @@ def test_walk_status_clean(walk):
     t.stats()
     t.forces(0.5, 0.01, walk=walk)
     t.build(p, m)  # checks the previous walk's status at its sync
+
+
+@pytest.mark.parametrize("bits,status,word", [(1, 5, "overflowed"), (2, 3, "corrupt"), (3, 5, "overflowed")])
+def test_walk_status_reported(bits, status, word):
+    """The walk status word reaches the caller: set from the host (as a walk
+    whose stack push was refused, bit 0, or that met a node with more than 8
+    children, bit 1, would leave it; no kernel is made to misbehave), it is
+    reported once by tc_tree_stats, and by the next tc_build when a walk's
+    status is pending; the failed build leaves the handle unbuilt, and a
+    rebuild clears the word."""
+    import paper_2412_01733_amd as tc
+    from paper_2412_01733_amd import _lib as L
+    p, m = _set(20000, 44)
+    t = tc.Tree().build(p, m).moments()
+    t.forces(0.5, 0.01)
+    lib = L.load()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev()).cuda_stream)
+    L.check(lib.tc_tree_set_walk_status(t._h, bits, stream))
+    with pytest.raises(L.TreecodeError) as e:
+        t.stats()
+    assert e.value.status == status and word in str(e.value), str(e.value)
+    t.stats()  # reported once
+    L.check(lib.tc_tree_set_walk_status(t._h, bits, stream))
+    with pytest.raises(L.TreecodeError) as e:
+        t.build(p, m)
+    assert e.value.status == status and word in str(e.value), str(e.value)
+    with pytest.raises(L.TreecodeError) as e:
+        t.forces(0.5, 0.01)
+    assert e.value.status == L.TC_ERR_STATE
+    t.build(p, m).moments()
+    acc, _ = t.forces(0.5, 0.01)
+    t.stats()
+    assert torch.isfinite(acc).all()
+    assert lib.tc_tree_set_walk_status(t._h, 4, stream) == L.TC_ERR_INVALID
