@@ -219,9 +219,9 @@ __device__ inline void add4(double* dst, double v0, double v1, double v2, double
 // a wave reduction.  It replays the wave's stored records when there are
 // valid ones and re-walks the tree otherwise.
 // The walk is bound by latency at full occupancy, so the timed forward walks
-// are held to 64 VGPRs (8 waves per SIMD); the FP64 one needs the request.
+// are held to 64 VGPRs (8 waves per SIMD); both need the request.
 template <bool F64, bool COUNT, bool ADJ, bool STORE>
-__global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu((F64 && !COUNT && !ADJ && !STORE) ? 8 : 1)))
+__global__ __launch_bounds__(kWalkThreads) __attribute__((amdgpu_waves_per_eu((!COUNT && !ADJ && !STORE) ? 8 : 1)))
 void k_walk(WalkArgs a)
 {
     static_assert(!(ADJ && (COUNT || STORE)), "the adjoint walk neither counts nor stores");
@@ -641,19 +641,42 @@ void k_walk(WalkArgs a)
             const Hot* g8 = &stg[w][8 * j];
             if (fast && __builtin_amdgcn_inverse_ballot_w64(mask)) {
                 // no opening test here, so the softening enters the distance chain
+                if constexpr (!F64) {
+                    // each slot's position and mass are read while the slot before it is
+                    // evaluated, so the LDS latency is not paid child by child (the FP64
+                    // walk's 32-byte reads gain nothing from it)
+                    float4 hc = *reinterpret_cast<const float4*>(&g8[0]);
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    if ((fast >> k) & 1u) {
-                        const Hot h = g8[k];
-                        const R dx = h.x - px, dy = h.y - py, dz = h.z - pz;
-                        const R ri = rsqrt_any(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
-                        const R mr = h.m * ri;
-                        const R mr3 = mr * (ri * ri);
-                        bx = fma(mr3, dx, bx);
-                        by = fma(mr3, dy, by);
-                        bz = fma(mr3, dz, bz);
-                        bp -= mr;
-                        if constexpr (COUNT) ++nint;
+                    for (int k = 0; k < 8; ++k) {
+                        const float4 hn = k < 7 ? *reinterpret_cast<const float4*>(&g8[k + 1]) : hc;
+                        if ((fast >> k) & 1u) {
+                            const R dx = hc.x - px, dy = hc.y - py, dz = hc.z - pz;
+                            const R ri = rsqrt_any(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
+                            const R mr = hc.w * ri;
+                            const R mr3 = mr * (ri * ri);
+                            bx = fma(mr3, dx, bx);
+                            by = fma(mr3, dy, by);
+                            bz = fma(mr3, dz, bz);
+                            bp -= mr;
+                            if constexpr (COUNT) ++nint;
+                        }
+                        hc = hn;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        if ((fast >> k) & 1u) {
+                            const Hot h = g8[k];
+                            const R dx = h.x - px, dy = h.y - py, dz = h.z - pz;
+                            const R ri = rsqrt_any(fma(dx, dx, fma(dy, dy, fma(dz, dz, eps2))));
+                            const R mr = h.m * ri;
+                            const R mr3 = mr * (ri * ri);
+                            bx = fma(mr3, dx, bx);
+                            by = fma(mr3, dy, by);
+                            bz = fma(mr3, dz, bz);
+                            bp -= mr;
+                            if constexpr (COUNT) ++nint;
+                        }
                     }
                 }
             }
