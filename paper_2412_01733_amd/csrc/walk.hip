@@ -257,7 +257,6 @@ void k_walk(WalkArgs a)
     __shared__ float sval[(ADJ && !F64) ? kWalkWaves : 1][2][4][64];
     __shared__ uint32_t rnode[ADJ ? kWalkWaves : 1][8];          // node of each pending slot
     __shared__ uint4 lbuf[STORE ? kWalkWaves : 1][kListBuf];
-    __shared__ RecHot<R> rbuf[ADJ ? kWalkWaves : 1][ADJ ? kReplayChunk : 1];
     R tau0;
     if constexpr (F64) tau0 = a.tau0_64;
     else tau0 = a.tau0_32;
@@ -474,6 +473,11 @@ void k_walk(WalkArgs a)
 
     bool replayed = false;
     if constexpr (ADJ) {
+        // a wave that replays its records never walks, so the replay chunk lives in
+        // the wave's (then unused) stack slice
+        static_assert(kGroups == 1 && sizeof(RecHot<R>) * kReplayChunk <= sizeof(uint4) * kStack,
+                      "replay chunk within the stack slice");
+        RecHot<R>* const rb = reinterpret_cast<RecHot<R>*>(&stk1[w][0]);
         if (a.lists) {
             const uint32_t len = uni(a.list_len[wave_id]);
             if (len != kListInvalid && len <= a.list_cap) {
@@ -493,11 +497,11 @@ void k_walk(WalkArgs a)
                             e.m = (float)nd.m;
                         }
                         e.node = rec.x; e.kind = rec.y; e.mlo = rec.z; e.mhi = rec.w;
-                        rbuf[w][lane] = e;
+                        rb[lane] = e;
                     }
                     wave_sync();
                     for (uint32_t r = 0; r < cn; ++r) {
-                        const RecHot<R> e = rbuf[w][r];  // one broadcast read
+                        const RecHot<R> e = rb[r];  // one broadcast read
                         const uint32_t node = uni(e.node), kind = uni(e.kind);
                         const uint64_t m = ((uint64_t)uni(e.mhi) << 32) | uni(e.mlo);
                         if (kind == 0) {
@@ -515,7 +519,7 @@ void k_walk(WalkArgs a)
                             leaf_terms(uni(a.nodes[node].first), uni(a.nodes[node].count), m);
                         }
                     }
-                    wave_sync();  // the next chunk overwrites rbuf
+                    wave_sync();  // the next chunk overwrites the buffer
                     fold();
                 }
                 src_flush();
