@@ -72,7 +72,8 @@ typedef void* (*tc_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*tc_free_fn)(void* ptr, void* stream, void* ctx);
 
 /* Install the allocator used by handles created afterwards (process-wide).
- * Passing NULL for both restores the default (hipMalloc / hipFree).  A handle
+ * Passing NULL for both restores the default (hipMallocAsync / hipFreeAsync on
+ * the call's stream, from the device's default memory pool).  A handle
  * frees a buffer it grows past on the stream of the growing call, and frees
  * everything in tc_tree_free after its enqueued work is done; a stream-ordered
  * allocator (the Python binding installs torch's caching allocator) needs no

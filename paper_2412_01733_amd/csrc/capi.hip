@@ -32,17 +32,19 @@ tc_status fail(tc_status st, const char* fmt, ...)
     return st;
 }
 
-void* default_alloc(size_t bytes, void*, void*)
+// Default allocator: stream-ordered (the device's default memory pool), so that
+// growing a buffer or freeing a handle never synchronises the device.
+void* default_alloc(size_t bytes, void* stream, void*)
 {
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    if (hipMallocAsync(&p, bytes, (hipStream_t)stream) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
     }
     return p;
 }
 
-void default_free(void* p, void*, void*) { (void)hipFree(p); }
+void default_free(void* p, void* stream, void*) { (void)hipFreeAsync(p, (hipStream_t)stream); }
 
 struct Buf {
     void* p = nullptr;

@@ -153,3 +153,43 @@ def test_walk_status_reported(bits, status, word):
     t.stats()
     assert torch.isfinite(acc).all()
     assert lib.tc_tree_set_walk_status(t._h, 4, stream) == L.TC_ERR_INVALID
+
+
+def test_default_allocator_is_stream_ordered():
+    """With no allocator installed the library takes its buffers from the
+    device's default memory pool in stream order (hipMallocAsync /
+    hipFreeAsync on the call's stream): a handle built, grown (a larger
+    rebuild frees and re-allocates on the stream) and freed through the C ABI
+    gives results bitwise equal to the same calls on torch's pool."""
+    import paper_2412_01733_amd as tc
+    from paper_2412_01733_amd import _lib as L
+    lib = L.load()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev()).cuda_stream)
+    sets = [_set(n, 45 + i) for i, n in enumerate((5000, 60000))]
+
+    def run(h):
+        outs = []
+        for p, m in sets:
+            acc = torch.empty((p.shape[0], 3), dtype=torch.float32, device=dev())
+            pot = torch.empty(p.shape[0], dtype=torch.float32, device=dev())
+            L.check(lib.tc_build(ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(m.data_ptr()), p.shape[0],
+                                 L.TC_F32, stream, ctypes.byref(h)))
+            L.check(lib.tc_moments(h, stream))
+            L.check(lib.tc_forces(h, 0.5, 0.01, 1.0, L.TC_WALK_F32C, 0, ctypes.c_void_p(acc.data_ptr()),
+                                  ctypes.c_void_p(pot.data_ptr()), stream))
+            outs.append((acc, pot))
+        torch.cuda.synchronize()
+        return outs
+
+    try:
+        assert lib.tc_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None) == L.TC_OK  # the default
+        h = ctypes.c_void_p()
+        got = run(h)
+        lib.tc_tree_free(h)
+    finally:
+        tc.treecode.bind_torch_allocator()
+    h = ctypes.c_void_p()
+    ref = run(h)
+    lib.tc_tree_free(h)
+    for (a, p), (ra, rp) in zip(got, ref):
+        assert torch.equal(a, ra) and torch.equal(p, rp)
