@@ -209,6 +209,8 @@ typedef struct {
     uint64_t visits_overlap;     /* TC_COUNT: evaluations of nodes whose particle range overlaps the
                                     range of the wavefront's targets (they may hold a target) */
     uint64_t visits_overlap_all_accept;  /* TC_COUNT: of those, evaluations every active lane accepts */
+    uint64_t list_bytes;     /* device bytes holding the stored interaction lists of the last
+                                tc_forces (16 bytes a record, 8192 records a wavefront), 0 if none */
 } tc_stats;
 
 /* Fill *out.  Synchronises `stream` when diagnostics, timings or a walk's

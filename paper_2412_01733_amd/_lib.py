@@ -58,6 +58,7 @@ class TcStats(ctypes.Structure):
         ("walk_single_steps", ctypes.c_uint64),
         ("visits_overlap", ctypes.c_uint64),
         ("visits_overlap_all_accept", ctypes.c_uint64),
+        ("list_bytes", ctypes.c_uint64),
     ]
 
 

@@ -791,6 +791,7 @@ tc_status tc_tree_stats(tc_tree* t, tc_stats* out, void* stream)
     }
     out->last_mode = (uint32_t)t->last_mode;
     out->lists_stored = t->lists_stored ? 1u : 0u;
+    out->list_bytes = t->lists_stored ? (uint64_t)walk_waves(t->n) * kListCap * sizeof(uint4) : 0u;
     if (t->state & 4u) {
         for (int k = 0; k < 3; ++k) out->momentum[k] = t->host->diag[k];
         out->sum_m_abs_a = t->host->diag[3];

@@ -224,7 +224,7 @@ class Tree:
                     visits_box_open=int(s.visits_box_open), visits_box_accept=int(s.visits_box_accept),
                     walk_steps=int(s.walk_steps), walk_single_steps=int(s.walk_single_steps),
                     visits_overlap=int(s.visits_overlap),
-                    visits_overlap_all_accept=int(s.visits_overlap_all_accept))
+                    visits_overlap_all_accept=int(s.visits_overlap_all_accept), list_bytes=int(s.list_bytes))
 
     def export(self, moments=True):
         st = self.stats()

@@ -30,13 +30,14 @@ def test_stats_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "treecode.h"\n'
                    'int main(void){printf("%zu %zu %zu", sizeof(tc_stats), offsetof(tc_stats, stage_ms),'
-                   ' offsetof(tc_stats, lists_stored)); return 0;}\n')
+                   ' offsetof(tc_stats, lists_stored)); printf(" %zu", offsetof(tc_stats, list_bytes)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
-    size, off_stage, off_lists = map(int, subprocess.check_output([str(exe)]).split())
+    size, off_stage, off_lists, off_bytes = map(int, subprocess.check_output([str(exe)]).split())
     S = _lib().TcStats
     assert ctypes.sizeof(S) == size
     assert S.stage_ms.offset == off_stage and S.lists_stored.offset == off_lists
+    assert S.list_bytes.offset == off_bytes
 
 
 def test_library_exports_every_symbol():

@@ -51,7 +51,9 @@ def test_backward_matches_oracle_adjoint(walk, theta, store):
     t = tc.Tree()
     t.build(torch.from_numpy(x).to(dev()), torch.from_numpy(m).to(dev())).moments()
     t.forces(theta, eps, G, walk=walk, count=True, store_lists=store)
-    assert t.stats()["lists_stored"] == store
+    st = t.stats()
+    assert st["lists_stored"] == store
+    assert st["list_bytes"] == (((n + 63) // 64) * 8192 * 16 if store else 0)  # one slice per wavefront
     dt = torch.float64 if walk == "f64" else torch.float32
     gpos, gmass = t.backward(torch.from_numpy(g).to(dev(), dt), torch.from_numpy(h).to(dev(), dt))
     torch.cuda.synchronize()
