@@ -54,6 +54,10 @@ constexpr int kBatchGroupsF64 = 4;  // the FP64 walk's 64-byte staged records (7
 // happen; it would be refused and flagged (status bit 0).
 constexpr int kStackDfs = 7 * 20 + 1;
 constexpr int kStackMulti = 272;
+// The FP64 walk's 64-byte staged records leave less room: with 256 entries its
+// 4-wave block (22 272 bytes) fits 7 to a CU's LDS, with 272 only 6 (the LDS is
+// allocated in 512-byte granules).
+constexpr int kStackMultiF64 = 256;
 // The adjoint walk keeps its gradients in LDS as well; it takes one group per
 // step and a depth-first stack (<= 141 groups), which keeps 7 waves per SIMD.
 constexpr int kStackSingle = 160;
@@ -233,7 +237,7 @@ void k_walk(WalkArgs a)
     using Hot = typename std::conditional<F64, Hot64, Hot32>::type;
     // groups per step and the stack they need
     constexpr int kGroups = ADJ ? 1 : (F64 ? kBatchGroupsF64 : kBatchGroups);
-    constexpr int kStack = kGroups == 1 ? kStackSingle : kStackMulti;
+    constexpr int kStack = kGroups == 1 ? kStackSingle : (F64 ? kStackMultiF64 : kStackMulti);
     constexpr int kStackBatch = kStack - kStackDfs - 7;
     // the stack of pending sibling groups: first node, child count, lanes that opened the parent
     // (several groups per step: three arrays, 13 bytes an entry, so that the deeper stack
