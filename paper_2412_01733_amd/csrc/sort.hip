@@ -17,9 +17,11 @@ constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortThreads = 256;          // 4 waves
 constexpr int kSortWaves = kSortThreads / 64;
-constexpr int kSortItems = 16;             // per lane
-constexpr int kWaveTile = 64 * kSortItems; // 1024 per wave
-constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 per block
+// 15 keys per lane: the scatter kernel's 52 240 bytes of LDS fit 3 blocks per CU
+// (16 keys, 55 312 bytes, fit only 2 in 512-byte allocation granules)
+constexpr int kSortItems = 15;             // per lane
+constexpr int kWaveTile = 64 * kSortItems; // 960 per wave
+constexpr int kSortTile = kSortThreads * kSortItems;  // 3840 per block
 
 __device__ inline uint32_t lane_id() { return threadIdx.x & 63; }
 

@@ -8,8 +8,8 @@ Bars (stated where they are asserted):
   * interaction counts: F64 equal to the oracle's; F32C may differ only for
     targets where a distance sits within FP32 rounding of the opening
     threshold, required on < 1% of targets.
-Inputs are seeded (workloads); sizes span several sort tiles (4096), walk
-waves (64) and ragged tails.
+Inputs are seeded (workloads); sizes span several sort tiles (3840 keys),
+scan tiles (4096), walk waves (64) and ragged tails.
 """
 import numpy as np
 import pytest
@@ -127,7 +127,7 @@ def test_theta_zero_is_direct_sum(walk):
 
 
 @pytest.mark.parametrize("walk", ["f32c", "f64"])
-@pytest.mark.parametrize("n", [0, 1, 2, 3, 63, 64, 65, 4095, 4096, 4097])
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 63, 64, 65, 3839, 3840, 3841, 4095, 4096, 4097, 7681])
 def test_small_and_ragged_sizes(n, walk):
     pos, m = workloads.plummer(max(n, 1), 900 + n)
     pos, m = pos[:n], m[:n]
