@@ -42,7 +42,7 @@ constexpr int kWalkThreads = 64 * kWalkWaves;
 constexpr uint32_t kXcdRun = 64;  // consecutive blocks one XCD takes at a time
 // A step of the walk takes up to kBatchGroups sibling groups off the stack and
 // stages all their children at once, 8 lanes per group.
-constexpr int kBatchGroups = 5;
+constexpr int kBatchGroups = 6;
 constexpr int kBatchGroupsF64 = 4;  // the FP64 walk's 64-byte staged records (7 waves per SIMD)
 // Stack bound.  Taking one group and pushing the groups of its opened
 // children (at most 8) grows the stack by at most 7 per level below the
@@ -53,10 +53,11 @@ constexpr int kBatchGroupsF64 = 4;  // the FP64 walk's 64-byte staged records (7
 // kStackBatch + 141 <= kStack.  A push beyond the stack therefore cannot
 // happen; it would be refused and flagged (status bit 0).
 constexpr int kStackDfs = 7 * 20 + 1;
-constexpr int kStackMulti = 272;
+// 248 entries: the F32C walk's 4-wave block (stack, 48 staged children) takes
+// 20 192 bytes and fits 8 to a CU's LDS (allocated in 512-byte granules).
+constexpr int kStackMulti = 248;
 // The FP64 walk's 64-byte staged records leave less room: with 256 entries its
-// 4-wave block (22 272 bytes) fits 7 to a CU's LDS, with 272 only 6 (the LDS is
-// allocated in 512-byte granules).
+// 4-wave block (22 272 bytes) fits 7 to a CU, with 272 only 6.
 constexpr int kStackMultiF64 = 256;
 // The adjoint walk keeps its gradients in LDS as well; it takes one group per
 // step and a depth-first stack (<= 141 groups), which keeps 7 waves per SIMD.
